@@ -1,0 +1,256 @@
+/*
+ * hermtile -- k-local quantum operations on n-qubit hermitian operators stored
+ * as lower-triangle tiles, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Orkan: cache-friendly simulation of quantum operations on
+ * hermitian operators" (arXiv 2604.15765).
+ * A hermitian N x N operator H (N = 2^n; a density matrix or an observable) is
+ * stored as the tiles T(ti,tj), ti >= tj, of edge M = 2^m of its lower tile
+ * triangle (Section III-B), and every k-local operation
+ *     H -> sum_a K_a H K_a^dagger,  K_a = I (x) L_a          (Eq. (1), Eq. (2))
+ * is applied in one read-modify-write pass over the stored tiles (Section
+ * III-C, Algorithms 2 and 3 and their appendix subroutines).
+ *
+ * Conventions used throughout
+ * ---------------------------
+ *  - Qubit q is bit q of a basis index (little-endian).
+ *  - Complex numbers are interleaved pairs of doubles (re, im).
+ *  - A k-local matrix is 2^k x 2^k, row-major; its local index bit l belongs
+ *    to targets[l] (the order the caller gives; the library sorts internally).
+ *  - Storage: tile (ti, tj) is tile number ti(ti+1)/2 + tj; its M^2 entries are
+ *    row-major; diagonal tiles hold all M^2 entries.  When N < M the library
+ *    uses one N x N tile instead of padding (the effective tile edge is
+ *    min(M, N)).  c128 entries are 16 bytes, c64 entries 8 bytes.
+ *  - Device memory: "device" pointers are HIP device addresses on the device
+ *    that was current when the handle was created.
+ *  - Streams: every call is enqueued on the handle's stream in order.  Calls
+ *    that return a value to a host pointer synchronise that stream first.
+ *  - Errors: every function returns an ht_status.  Argument errors are
+ *    detected before anything is enqueued and leave the operator untouched;
+ *    ht_last_error() then describes the problem.  HIP failures return
+ *    HT_EDEVICE with the HIP error string.
+ *  - Thread safety: a handle must not be used from two threads at once;
+ *    distinct handles are independent.
+ */
+#ifndef HERMTILE_H
+#define HERMTILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ht_herm ht_herm; /* opaque handle: one tiled hermitian operator */
+
+typedef enum {
+  HT_C128 = 0, /* complex double storage, FP64 arithmetic */
+  HT_C64 = 1   /* complex float storage, FP64 arithmetic and reductions */
+} ht_dtype;
+
+typedef enum {
+  HT_SCHRODINGER = 0, /* H -> sum_a L_a H L_a^dagger (states) */
+  HT_HEISENBERG = 1   /* H -> sum_a L_a^dagger H L_a (observables) */
+} ht_picture;
+
+typedef enum {
+  HT_OK = 0,
+  HT_EINVAL = 1,       /* invalid argument; nothing was enqueued */
+  HT_ENOMEM = 2,       /* device allocation failed or buffer too small */
+  HT_EDEVICE = 3,      /* a HIP call failed */
+  HT_EUNSUPPORTED = 4  /* valid request outside what this build implements */
+} ht_status;
+
+/* Smallest and largest tile edge exponent accepted by ht_herm_create. */
+#define HT_MIN_TILE_LOG2 1
+#define HT_MAX_TILE_LOG2 8
+/* Largest qubit count accepted (c128 at n = 17 is 137 GB of storage). */
+#define HT_MAX_QUBITS 18
+
+/* ---------------------------------------------------------------- sizes -- */
+
+/* Bytes of tiled storage for an n-qubit operator: N(N + M')/2 entries with
+ * M' = min(2^tile_log2, N) (Section III-B; Table I gives the padded sizes).
+ * Returns 0 if n or tile_log2 is out of range or the dtype is unknown.
+ * Pure host function; needs no GPU. */
+size_t ht_storage_bytes(int n, int tile_log2, ht_dtype dtype);
+
+/* Effective tile edge exponent used for an n-qubit operator:
+ * min(tile_log2, n).  Returns -1 on invalid input.  Pure host function. */
+int ht_effective_tile_log2(int n, int tile_log2);
+
+/* ------------------------------------------------------------- lifetime -- */
+
+/* Create a handle for an n-qubit hermitian operator with tile edge
+ * 2^tile_log2 and storage type dtype.
+ *   dev_buf    NULL: the library allocates the storage and frees it in
+ *              ht_herm_destroy.  Non-NULL: a device buffer of buf_bytes bytes
+ *              owned by the caller (for example a torch tensor); it must hold
+ *              ht_storage_bytes(...) bytes, be 256-byte aligned, and outlive
+ *              the handle.  The library never frees it.
+ *   hip_stream the hipStream_t every call of this handle is enqueued on
+ *              (NULL: the null stream).  Owned by the caller.
+ *   out        receives the handle.
+ * The storage content is undefined until one of the init calls runs.
+ * Errors: HT_EINVAL (n, tile_log2, dtype, alignment, out == NULL),
+ * HT_ENOMEM (allocation failed or buf_bytes too small), HT_EDEVICE. */
+ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, size_t buf_bytes,
+                         void* hip_stream, ht_herm** out);
+
+/* Destroy a handle: waits for its stream, frees what the library allocated.
+ * Accepts NULL. */
+ht_status ht_herm_destroy(ht_herm* h);
+
+/* Replace the stream future calls are enqueued on (NULL: null stream). */
+ht_status ht_herm_set_stream(ht_herm* h, void* hip_stream);
+
+/* Describe a handle.  Any output pointer may be NULL.  dev_ptr receives the
+ * device address of the tiled storage (tile 0, entry 0). */
+ht_status ht_herm_info(const ht_herm* h, int* n, int* tile_log2, int* dtype, void** dev_ptr,
+                       size_t* bytes);
+
+/* Wait until everything enqueued on the handle's stream has finished. */
+ht_status ht_herm_synchronize(ht_herm* h);
+
+/* ---------------------------------------------------------- init and IO -- */
+
+/* H = 0. */
+ht_status ht_herm_init_zero(ht_herm* h);
+
+/* H = scale * I (scale = 1/N gives the maximally mixed state). */
+ht_status ht_herm_init_identity(ht_herm* h, double scale);
+
+/* H = the hermitian matrix whose lower triangle (i >= j) is that of the dense
+ * complex N x N row-major matrix A with leading dimension ld >= N (complex
+ * entries).  Entries above the diagonal of A are not read: the stored upper
+ * halves of diagonal tiles are set to the conjugates of the lower ones.
+ * on_device != 0: A is a device pointer; 0: a host pointer (copied in; this
+ * needs a temporary N x N device buffer).  A is not retained. */
+ht_status ht_herm_init_dense(ht_herm* h, const double* A, int64_t ld, int on_device);
+
+/* H = G G^dagger for a complex N x rank matrix G, row-major (rank entries per
+ * row), 1 <= rank <= 4096.  on_device as above.  A normalised density matrix
+ * follows with ht_trace and ht_scale. */
+ht_status ht_herm_init_lowrank(ht_herm* h, const double* G, int rank, int on_device);
+
+/* H = sum_t coeffs[t] P_t for Pauli strings P_t; codes is nterms x n (host,
+ * row-major), codes[t*n + q] in {0=I, 1=X, 2=Y, 3=Z} acting on qubit q;
+ * coeffs is host, real.  1 <= nterms <= 65536. */
+ht_status ht_herm_init_pauli_sum(ht_herm* h, int nterms, const uint8_t* codes,
+                                 const double* coeffs);
+
+/* Write the dense N x N matrix represented by H (entries i >= j from storage,
+ * entries i < j as conjugates of their mirrors) to out, row-major, leading
+ * dimension ld >= N, complex128.  on_device: out is a device pointer (else
+ * host; the call then synchronises). */
+ht_status ht_herm_to_dense(const ht_herm* h, double* out, int64_t ld, int on_device);
+
+/* Read count entries H[rows[e], cols[e]] of the represented matrix (any
+ * 0 <= row, col < N; entries above the diagonal come back as conjugates of
+ * their stored mirrors) into out (host, 2*count doubles).  rows and cols are
+ * host arrays.  Synchronises.  1 <= count <= 2^24. */
+ht_status ht_herm_get_entries(const ht_herm* h, int64_t count, const int64_t* rows,
+                              const int64_t* cols, double* out);
+
+/* Copy raw storage bytes [offset, offset + nbytes) to the host buffer out.
+ * Synchronises. */
+ht_status ht_herm_read_raw(const ht_herm* h, size_t offset, size_t nbytes, void* out);
+
+/* dst = src (same n, tile edge and dtype). */
+ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
+
+/* ------------------------------------------------------------- hot path -- */
+
+/* Apply a k-qubit unitary (or any 2^k x 2^k matrix) U by conjugation:
+ * Schroedinger H -> U H U^dagger, Heisenberg H -> U^dagger H U
+ * (Eq. (2) with one Kraus operator; Section II-A: unitaries keep the direct
+ * two-sided block update).  k in {1, 2}; targets: k distinct qubits in
+ * [0, n); U: host, 2 * 4^k doubles, row-major, interleaved complex.  U is not
+ * checked for unitarity.  Enqueued asynchronously; U is copied before return. */
+ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,
+                           ht_picture picture);
+
+/* Apply the quantum operation with Kraus operators L_0..L_{r-1}:
+ * Schroedinger H -> sum_a L_a H L_a^dagger (Eq. (1)), Heisenberg
+ * H -> sum_a L_a^dagger H L_a.  k in {1, 2}; 1 <= r <= 4^k; kraus: host,
+ * r consecutive 2^k x 2^k row-major complex matrices (2 * r * 4^k doubles).
+ * For r > 1 the map is applied through its transfer matrix (Eq. (3),
+ * built on the host in FP64).  Trace-preservation is not required (the
+ * algorithms hold for trace non-increasing maps, Section IV-A).  Enqueued
+ * asynchronously; kraus is copied before return. */
+ht_status ht_apply_channel(ht_herm* h, int k, const int* targets, int r, const double* kraus,
+                           ht_picture picture);
+
+/* ----------------------------------------------------------- reductions -- */
+
+/* tr H = sum_i Re h_ii, accumulated in FP64 in a fixed order (deterministic).
+ * out: host.  Synchronises. */
+ht_status ht_trace(const ht_herm* h, double* out);
+
+/* tr(A B) = Re sum_ij a_ij conj(b_ij) over the represented matrices, from the
+ * tiles (Section III-C closing formula, with the off-diagonal tile sum strict:
+ * diagonal tiles once, strictly lower tiles twice).  A and B must have the
+ * same n, tile edge and dtype.  FP64, deterministic.  Synchronises. */
+ht_status ht_expectation(const ht_herm* a, const ht_herm* b, double* out);
+
+/* tr(H O) for O = sum_t coeffs[t] P_t (codes/coeffs as in
+ * ht_herm_init_pauli_sum), read directly from the N entries each string
+ * touches.  FP64, deterministic.  Synchronises. */
+ht_status ht_expectation_pauli_sum(const ht_herm* h, int nterms, const uint8_t* codes,
+                                   const double* coeffs, double* out);
+
+/* H = alpha * H (for example alpha = 1 / tr H to normalise). */
+ht_status ht_scale(ht_herm* h, double alpha);
+
+/* --------------------------------------------------------- diagnostics -- */
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* ht_last_error(void);
+
+/* Per-kernel timing of hot-path launches, for measurement.  When enabled,
+ * every conjugation launch of this handle is bracketed by HIP events on the
+ * handle's stream.  ht_profile_read synchronises and returns, per kernel
+ * class (one class per storage type, k, number of tile-selecting targets and
+ * form; ht_kernel_class_name(i) names class i), the number of launches, the
+ * summed event time in milliseconds and the summed algorithmic bytes (every
+ * stored entry read once and written once).  Entries 0..max_classes-1 of the
+ * three arrays are written (any may be NULL); *nclasses receives the total
+ * number of classes.  ht_profile_reset clears the sums. */
+ht_status ht_profile_enable(ht_herm* h, int enable);
+ht_status ht_profile_read(ht_herm* h, int max_classes, int* nclasses, int64_t* launches,
+                          double* ms, double* bytes);
+ht_status ht_profile_reset(ht_herm* h);
+/* Name of kernel class idx ("c128_k1_c0_direct", ...); NULL if out of range. */
+const char* ht_kernel_class_name(int idx);
+
+/* Launch tuning of the conjugation pass, process-wide; it changes speed, never
+ * results.  "conj_wg_per_cu" (1..64, default 8): workgroups per compute unit
+ * of the grid-stride grid.  "conj_block_threads" (64, 128 or 256, default
+ * 256): workgroup size.  HT_EINVAL for an unknown name or value. */
+ht_status ht_set_tuning(const char* name, int64_t value);
+
+/* Pure host function (no GPU): the per-op preparation the library performs
+ * before a launch, exposed for testing.  Given the same arguments as
+ * ht_apply_channel (r = 1 for a unitary) and an operator shape (n, tile_log2),
+ * writes
+ *   sorted_targets[k]  targets in ascending order,
+ *   *ncross            how many targets lie at or above the effective tile
+ *                      exponent (they select tiles rather than entries),
+ *   *form              0: direct two-sided form (coef holds the 2^k x 2^k
+ *                      matrix A, applied as A h A^dagger), 1: transfer form
+ *                      (coef holds the 4^k x 4^k matrix S acting on the
+ *                      row-major vector of a block, S = sum_a A_a (x) conj(A_a)),
+ *   coef               interleaved complex, row-major: 2 * 4^k doubles for
+ *                      form 0, 2 * 16^k doubles for form 1 (512 always suffice),
+ * where the A_a are the caller's operators with their local bits reordered to
+ * ascending target order and, in the Heisenberg picture, adjoined. */
+ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
+                        const double* kraus, ht_picture picture, int* sorted_targets,
+                        int* ncross, int* form, double* coef);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERMTILE_H */

@@ -1,0 +1,339 @@
+"""hermtile: k-local quantum operations on tiled hermitian operators (MI355X).
+
+Thin Python binding of the C-ABI in ``include/hermtile.h``: argument
+marshalling only.  Every step of the computation runs in the HIP kernels of
+``libhermtile.so``; PyTorch provides device memory and streams.  Importing the
+package fails if the library has not been built (``__graft_entry__.build()``
+or ``python paper_2604_15765_amd/build_ext.py``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # first: the library must bind to the HIP runtime torch has loaded
+
+__all__ = ["Herm", "lib", "SCHRODINGER", "HEISENBERG", "HermError", "storage_bytes",
+           "effective_tile_log2", "prepare_op", "kernel_class_names", "set_tuning"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhermtile.so")
+
+SCHRODINGER = 0
+HEISENBERG = 1
+_DTYPES = {"c128": 0, "c64": 1}
+_STATUS = {0: "HT_OK", 1: "HT_EINVAL", 2: "HT_ENOMEM", 3: "HT_EDEVICE", 4: "HT_EUNSUPPORTED"}
+
+
+class HermError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _hip_runtime_copies():
+    """Paths of every libamdhip64 mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    copies = _hip_runtime_copies()
+    if len(copies) > 1:
+        raise ImportError(f"two HIP runtimes are loaded ({sorted(copies)}); import torch first")
+    c_int, c_int64, c_double, c_size_t, vp = (ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                              ctypes.c_size_t, ctypes.c_void_p)
+    P = ctypes.POINTER
+    sig = {
+        "ht_storage_bytes": (c_size_t, [c_int, c_int, c_int]),
+        "ht_effective_tile_log2": (c_int, [c_int, c_int]),
+        "ht_herm_create": (c_int, [c_int, c_int, c_int, vp, c_size_t, vp, P(vp)]),
+        "ht_herm_destroy": (c_int, [vp]),
+        "ht_herm_set_stream": (c_int, [vp, vp]),
+        "ht_herm_info": (c_int, [vp, P(c_int), P(c_int), P(c_int), P(vp), P(c_size_t)]),
+        "ht_herm_synchronize": (c_int, [vp]),
+        "ht_herm_init_zero": (c_int, [vp]),
+        "ht_herm_init_identity": (c_int, [vp, c_double]),
+        "ht_herm_init_dense": (c_int, [vp, vp, c_int64, c_int]),
+        "ht_herm_init_lowrank": (c_int, [vp, vp, c_int, c_int]),
+        "ht_herm_init_pauli_sum": (c_int, [vp, c_int, vp, vp]),
+        "ht_herm_to_dense": (c_int, [vp, vp, c_int64, c_int]),
+        "ht_herm_get_entries": (c_int, [vp, c_int64, vp, vp, vp]),
+        "ht_herm_read_raw": (c_int, [vp, c_size_t, c_size_t, vp]),
+        "ht_herm_copy": (c_int, [vp, vp]),
+        "ht_apply_unitary": (c_int, [vp, c_int, vp, vp, c_int]),
+        "ht_apply_channel": (c_int, [vp, c_int, vp, c_int, vp, c_int]),
+        "ht_trace": (c_int, [vp, P(c_double)]),
+        "ht_expectation": (c_int, [vp, vp, P(c_double)]),
+        "ht_expectation_pauli_sum": (c_int, [vp, c_int, vp, vp, P(c_double)]),
+        "ht_scale": (c_int, [vp, c_double]),
+        "ht_last_error": (ctypes.c_char_p, []),
+        "ht_profile_enable": (c_int, [vp, c_int]),
+        "ht_profile_read": (c_int, [vp, c_int, P(c_int), vp, vp, vp]),
+        "ht_profile_reset": (c_int, [vp]),
+        "ht_kernel_class_name": (ctypes.c_char_p, [c_int]),
+        "ht_prepare_op": (c_int, [c_int, c_int, c_int, vp, c_int, vp, c_int, vp, P(c_int), P(c_int), vp]),
+        "ht_set_tuning": (c_int, [ctypes.c_char_p, c_int64]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise HermError(status, lib.ht_last_error().decode())
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def storage_bytes(n: int, tile_log2: int, dtype: str = "c128") -> int:
+    return int(lib.ht_storage_bytes(n, tile_log2, _DTYPES[dtype]))
+
+
+def effective_tile_log2(n: int, tile_log2: int) -> int:
+    return int(lib.ht_effective_tile_log2(n, tile_log2))
+
+
+def kernel_class_names():
+    out = []
+    i = 0
+    while True:
+        s = lib.ht_kernel_class_name(i)
+        if s is None:
+            return out
+        out.append(s.decode())
+        i += 1
+
+
+def set_tuning(name: str, value: int) -> None:
+    _check(lib.ht_set_tuning(name.encode(), int(value)))
+
+
+def prepare_op(n: int, tile_log2: int, targets: Sequence[int], mats, picture: int = SCHRODINGER):
+    """ht_prepare_op: returns (sorted_targets, ncross, form, coef complex array)."""
+    mats = _c128(mats)
+    if mats.ndim == 2:
+        mats = mats[None]
+    k = len(targets)
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    st = np.zeros(2, dtype=np.int32)
+    nc = ctypes.c_int()
+    form = ctypes.c_int()
+    coef = np.zeros(2 * 256, dtype=np.float64)
+    _check(lib.ht_prepare_op(n, tile_log2, k, _ptr(t), mats.shape[0], _ptr(mats), picture,
+                             _ptr(st), ctypes.byref(nc), ctypes.byref(form), _ptr(coef)))
+    d = 1 << k
+    ne = d * d if form.value == 0 else d ** 4
+    c = coef[:2 * ne].view(np.complex128)
+    side = d if form.value == 0 else d * d
+    return list(st[:k]), nc.value, form.value, c.reshape(side, side).copy()
+
+
+class Herm:
+    """One tiled hermitian operator on the GPU (an ``ht_herm`` handle).
+
+    The tiled storage is a torch uint8 tensor owned by this object and lent to
+    the library; calls are enqueued on ``stream`` (default: torch's current
+    stream of ``device``)."""
+
+    def __init__(self, n: int, tile_log2: int = 5, dtype: str = "c128",
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        if dtype not in _DTYPES:
+            raise ValueError(f"dtype must be one of {list(_DTYPES)}")
+        self.n = int(n)
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = storage_bytes(n, tile_log2, dtype)
+        if nbytes == 0:
+            raise HermError(1, f"invalid n={n} or tile_log2={tile_log2}")
+        with torch.cuda.device(self.device):
+            self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _check(lib.ht_herm_create(self.n, tile_log2, _DTYPES[dtype], ctypes.c_void_p(self.buffer.data_ptr()),
+                                      nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.tile_log2 = effective_tile_log2(n, tile_log2)
+        self.nbytes = nbytes
+
+    # lifetime ----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib.ht_herm_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def set_stream(self, stream: torch.cuda.Stream) -> None:
+        _check(lib.ht_herm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def synchronize(self) -> None:
+        _check(lib.ht_herm_synchronize(self._h))
+
+    # init / IO ---------------------------------------------------------
+    def init_zero(self) -> "Herm":
+        _check(lib.ht_herm_init_zero(self._h))
+        return self
+
+    def init_identity(self, scale: float = 1.0) -> "Herm":
+        _check(lib.ht_herm_init_identity(self._h, float(scale)))
+        return self
+
+    def init_dense(self, A) -> "Herm":
+        if isinstance(A, torch.Tensor) and A.is_cuda:
+            A = A.contiguous()
+            if A.dtype != torch.complex128:
+                raise TypeError("device matrices must be complex128")
+            _check(lib.ht_herm_init_dense(self._h, ctypes.c_void_p(A.data_ptr()), A.shape[1], 1))
+            self._keep = A
+            return self
+        A = _c128(A)
+        _check(lib.ht_herm_init_dense(self._h, _ptr(A), A.shape[1], 0))
+        return self
+
+    def init_lowrank(self, G) -> "Herm":
+        if isinstance(G, torch.Tensor) and G.is_cuda:
+            G = G.contiguous()
+            _check(lib.ht_herm_init_lowrank(self._h, ctypes.c_void_p(G.data_ptr()), G.shape[1], 1))
+            self._keep = G
+            return self
+        G = _c128(G)
+        _check(lib.ht_herm_init_lowrank(self._h, _ptr(G), G.shape[1], 0))
+        return self
+
+    def init_pauli_sum(self, codes, coeffs) -> "Herm":
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        _check(lib.ht_herm_init_pauli_sum(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs)))
+        return self
+
+    def to_dense(self) -> np.ndarray:
+        N = 1 << self.n
+        out = np.empty((N, N), dtype=np.complex128)
+        _check(lib.ht_herm_to_dense(self._h, _ptr(out), N, 0))
+        return out
+
+    def get_entries(self, rows, cols) -> np.ndarray:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.empty(rows.shape[0], dtype=np.complex128)
+        _check(lib.ht_herm_get_entries(self._h, rows.shape[0], _ptr(rows), _ptr(cols), _ptr(out)))
+        return out
+
+    def read_raw(self, offset: int = 0, nbytes: Optional[int] = None) -> np.ndarray:
+        if nbytes is None:
+            nbytes = self.nbytes - offset
+        out = np.empty(nbytes, dtype=np.uint8)
+        _check(lib.ht_herm_read_raw(self._h, offset, nbytes, _ptr(out)))
+        return out
+
+    def raw_entries(self) -> np.ndarray:
+        """The whole tiled storage as a complex128 array (c64 widened)."""
+        raw = self.read_raw()
+        if self.dtype == "c128":
+            return raw.view(np.complex128).copy()
+        return raw.view(np.complex64).astype(np.complex128)
+
+    def copy_from(self, other: "Herm") -> "Herm":
+        _check(lib.ht_herm_copy(self._h, other._h))
+        return self
+
+    # hot path ----------------------------------------------------------
+    def apply_unitary(self, targets: Sequence[int], U, picture: int = SCHRODINGER) -> None:
+        U = _c128(U)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_apply_unitary(self._h, len(targets), _ptr(t), _ptr(U), picture))
+
+    def apply_channel(self, targets: Sequence[int], kraus, picture: int = SCHRODINGER) -> None:
+        K = _c128(kraus)
+        if K.ndim == 2:
+            K = K[None]
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_apply_channel(self._h, len(targets), _ptr(t), K.shape[0], _ptr(K), picture))
+
+    def apply_op(self, op, picture: int = SCHRODINGER) -> None:
+        """Apply an op with ``kind``, ``targets`` and ``mats`` (see ``synth.Op``)."""
+        if op.kind == "unitary":
+            self.apply_unitary(op.targets, op.mats[0], picture)
+        else:
+            self.apply_channel(op.targets, op.mats, picture)
+
+    # reductions --------------------------------------------------------
+    def trace(self) -> float:
+        out = ctypes.c_double()
+        _check(lib.ht_trace(self._h, ctypes.byref(out)))
+        return out.value
+
+    def expectation(self, other: "Herm") -> float:
+        out = ctypes.c_double()
+        _check(lib.ht_expectation(self._h, other._h, ctypes.byref(out)))
+        return out.value
+
+    def expectation_pauli_sum(self, codes, coeffs) -> float:
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        out = ctypes.c_double()
+        _check(lib.ht_expectation_pauli_sum(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs),
+                                            ctypes.byref(out)))
+        return out.value
+
+    def scale(self, alpha: float) -> None:
+        _check(lib.ht_scale(self._h, float(alpha)))
+
+    # measurement -------------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        _check(lib.ht_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self) -> None:
+        _check(lib.ht_profile_reset(self._h))
+
+    def profile_read(self) -> dict:
+        nmax = 64
+        nc = ctypes.c_int()
+        launches = np.zeros(nmax, dtype=np.int64)
+        ms = np.zeros(nmax, dtype=np.float64)
+        by = np.zeros(nmax, dtype=np.float64)
+        _check(lib.ht_profile_read(self._h, nmax, ctypes.byref(nc), _ptr(launches), _ptr(ms), _ptr(by)))
+        names = kernel_class_names()
+        return {names[i]: dict(launches=int(launches[i]), ms=float(ms[i]), bytes=float(by[i]))
+                for i in range(nc.value) if launches[i] > 0}

@@ -1,0 +1,117 @@
+// The conjugation pass: H -> sum_a K_a H K_a^dagger on tiled storage.
+//
+// One kernel template covers intra-tile operations (Algorithm 2, c = 0),
+// operations whose targets select tiles (Algorithm 3 with Subroutines 2-4,
+// c = 1) and two-qubit operations on two tile-selecting qubits (c = 2), for
+// k = 1, 2 and for the direct (A h A^dagger) and transfer-matrix forms.  The
+// per-lane arithmetic lives in ht_geom.h; this file holds the grid-stride
+// driver and the runtime dispatch.
+//
+// The pass is a streaming read-modify-write of every stored entry (1-4 FP64
+// flops per byte), so it is bound by HBM bandwidth; there is no matrix-core
+// work in it.  Each wave owns whole groups, one at a time, and the blocks of a
+// group are disjoint, so no synchronisation is needed.
+#include "ht_geom.h"
+#include "ht_internal.h"
+
+namespace ht {
+
+LaunchTuning& tuning() {
+  static LaunchTuning t;
+  return t;
+}
+
+template <typename T, int K, int C, int FORM>
+__global__ void __launch_bounds__(256)
+    conj_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
+                const double* __restrict__ coef) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint32_t nblk = 1u << (2 * g.F);
+  const DirectMem<T> mem{h};
+  if constexpr (K == 2 && FORM == 1) cf.p = coef;  // 16 x 16 transfer matrix, read-only
+  for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
+    GroupCtx<C> gc;
+    group_ctx<K, C>(grp, g, gc);
+    for (uint32_t job = 0; job < g.jobs; ++job) {
+      const uint32_t b = job * 64u + lane;
+      if (b < nblk) conj_block<K, C, FORM>(mem, g, gc, cf, b);
+    }
+  }
+}
+
+template <typename T, int K, int C, int FORM>
+static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const double* coef_dev,
+                           int num_cu, hipStream_t s) {
+  ConjGeom<K, C> g = make_geom<K, C>(n, m, op.sorted);
+  Coef<K, FORM> cf;
+  if constexpr (K == 2 && FORM == 1) {
+    cf.p = nullptr;  // the kernel reads coef_dev
+  } else {
+    for (int i = 0; i < 2 * Coef<K, FORM>::NE; ++i) cf.c[i] = op.coef[i];
+  }
+  const int threads = tuning().block_threads;
+  const uint64_t waves_per_wg = (uint64_t)threads / 64;
+  uint64_t wgs = (g.ngroups + waves_per_wg - 1) / waves_per_wg;
+  const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
+  if (wgs > cap) wgs = cap;
+  if (wgs < 1) wgs = 1;
+  hipLaunchKernelGGL((conj_kernel<T, K, C, FORM>), dim3((unsigned)wgs), dim3(threads), 0, s,
+                     reinterpret_cast<typename store2<T>::type*>(buf), g, cf, coef_dev);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch_dtype(void* buf, int n, int m, const PreparedOp& op,
+                                 const double* coef_dev, int num_cu, hipStream_t s) {
+  const int k = op.k, c = op.ncross, f = op.form;
+#define HT_CASE(K_, C_, F_)                                                   \
+  if (k == K_ && c == C_ && f == F_)                                          \
+    return launch_t<T, K_, C_, F_>(buf, n, m, op, coef_dev, num_cu, s);
+  HT_CASE(1, 0, 0)
+  HT_CASE(1, 0, 1)
+  HT_CASE(1, 1, 0)
+  HT_CASE(1, 1, 1)
+  HT_CASE(2, 0, 0)
+  HT_CASE(2, 0, 1)
+  HT_CASE(2, 1, 0)
+  HT_CASE(2, 1, 1)
+  HT_CASE(2, 2, 0)
+  HT_CASE(2, 2, 1)
+#undef HT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_conj(int dtype, void* buf, int n, int m, const PreparedOp& op,
+                       const double* coef_dev, int num_cu, hipStream_t s) {
+  if (dtype == 0) return dispatch_dtype<double>(buf, n, m, op, coef_dev, num_cu, s);
+  if (dtype == 1) return dispatch_dtype<float>(buf, n, m, op, coef_dev, num_cu, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ coefficient upload
+
+struct UploadChunk {
+  double v[128];
+};
+
+__global__ void upload_kernel(double* __restrict__ dst, UploadChunk c, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = c.v[i];
+}
+
+hipError_t launch_upload(double* dst, const double* src, int count, hipStream_t s) {
+  for (int off = 0; off < count; off += 128) {
+    UploadChunk c;
+    const int len = count - off < 128 ? count - off : 128;
+    for (int i = 0; i < len; ++i) c.v[i] = src[off + i];
+    hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(128), 0, s, dst + off, c, len);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ht

@@ -1,0 +1,324 @@
+// Index arithmetic and the per-lane body of the tiled conjugation pass.
+//
+// Storage (Section III-B): tile (ti, tj), ti >= tj, is tile number
+// ti(ti+1)/2 + tj; its M x M entries (M = 2^m) are row-major.
+//
+// Work decomposition (Section III-C generalised to k <= 2 targets):
+//  * targets below m ("intra") address entries inside a tile, targets at or
+//    above m ("cross", C of them) address tiles;
+//  * removing the C cross bits from the tile indices leaves a reduced tile
+//    grid of NtS = (N/M)/2^C rows; each pair (Ti >= Tj) of it is a "group":
+//    the 2^C x 2^C tiles (ins(Ti, X), ins(Tj, Y)) that the operation mixes;
+//  * a tile above the diagonal is reached through its stored mirror, read and
+//    written conjugated and transposed (Algorithm 3 case B, Subroutine 3);
+//  * inside a group, a block is fixed by its base row p and base column q
+//    (positions inside a tile with the intra target bits cleared); block
+//    (p, q) holds the 2^k x 2^k entries of Eq. (2): local row u = (X, ui),
+//    local column v = (Y, vi), entry (X-tile, p + dep(ui), Y-tile, q + dep(vi)).
+//  * one lane updates one block in registers; the 64 lanes of a wave take an
+//    8 x 8 patch of (p, q) so that both a stored tile (rows p, 8 consecutive
+//    columns q) and a mirrored one (rows q, 8 consecutive columns p) are read
+//    as eight whole 128-byte lines per load instruction.
+//  * groups on the diagonal of the reduced grid (Ti == Tj, C > 0) contain
+//    each off-diagonal stored tile twice (directly and as a mirror); there
+//    block (p, q) with p > q also writes the conjugate results of block
+//    (q, p), which is skipped, and block (p, p) writes only entries whose
+//    tile lies on or below the diagonal (the role of Subroutine 4).
+// Every stored entry is written by exactly one lane per pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ht {
+
+#define HT_HD __host__ __device__ inline
+
+struct cd {
+  double re, im;
+};
+HT_HD cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+HT_HD cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// acc + a * b
+HT_HD cd cfma(cd acc, cd a, cd b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + a * conj(b)
+HT_HD cd cfma_cj(cd acc, cd a, cd b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.im, b.re, acc.im);
+  acc.im = fma(-a.re, b.im, acc.im);
+  return acc;
+}
+HT_HD cd conjg(cd a) { return {a.re, -a.im}; }
+
+// Storage element of the two dtypes: an interleaved (re, im) pair.
+template <typename T>
+struct store2;
+template <>
+struct store2<double> {
+  using type = double2;
+};
+template <>
+struct store2<float> {
+  using type = float2;
+};
+
+template <typename T>
+HT_HD cd load_c(const typename store2<T>::type* p, uint32_t off) {
+  typename store2<T>::type v = p[off];
+  return {(double)v.x, (double)v.y};
+}
+template <typename T>
+HT_HD void store_c(typename store2<T>::type* p, uint32_t off, cd v) {
+  typename store2<T>::type s;
+  s.x = (T)v.re;
+  s.y = (T)v.im;
+  p[off] = s;
+}
+
+// Insert a zero bit at position pos: bits >= pos move up by one.
+HT_HD uint32_t ins0(uint32_t x, int pos) {
+  const uint32_t lo = x & ((1u << pos) - 1u);
+  return ((x ^ lo) << 1) | lo;
+}
+
+HT_HD uint64_t tri64(uint64_t t) { return t * (t + 1) / 2; }
+
+// g -> (ti, tj) with g = ti(ti+1)/2 + tj, 0 <= tj <= ti.
+HT_HD void tri_decode(uint64_t g, uint32_t& ti, uint32_t& tj) {
+  uint64_t t = (uint64_t)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
+  while (tri64(t) > g) --t;
+  while (tri64(t + 1) <= g) ++t;
+  ti = (uint32_t)t;
+  tj = (uint32_t)(g - tri64(t));
+}
+
+// Geometry of one conjugation pass with K targets of which C are cross.
+template <int K, int C>
+struct ConjGeom {
+  static constexpr int KI = K - C;
+  int m;                       // effective tile exponent
+  int F;                       // free bits per tile dimension: m - KI
+  int s;                       // patch exponent: min(3, F)
+  int ipos[KI > 0 ? KI : 1];   // intra target bits, ascending, < m
+  int cpos[C > 0 ? C : 1];     // cross targets minus m, ascending
+  uint32_t jobs;               // 64-block patches per group: ceil(4^F / 64)
+  uint64_t ngroups;            // NtS (NtS + 1) / 2
+};
+
+// Deposit the bits of x into the positions that are not intra targets.
+template <int KI>
+HT_HD uint32_t deposit_free(uint32_t x, const int* ipos) {
+#pragma unroll
+  for (int l = 0; l < KI; ++l) x = ins0(x, ipos[l]);
+  return x;
+}
+
+// Intra offset of local intra index ui: bit l of ui placed at ipos[l].
+template <int KI>
+HT_HD uint32_t dep_intra(int ui, const int* ipos) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int l = 0; l < KI; ++l) r |= (uint32_t)((ui >> l) & 1) << ipos[l];
+  return r;
+}
+
+// Tile index with the cross bits of X inserted at cpos (ascending).
+template <int C>
+HT_HD uint32_t ins_cross(uint32_t t, uint32_t X, const int* cpos) {
+#pragma unroll
+  for (int l = 0; l < C; ++l) t = ins0(t, cpos[l]) | (((X >> l) & 1u) << cpos[l]);
+  return t;
+}
+
+// Block index b (0 <= b < 4^F) -> base indices (pidx, qidx) in [0, 2^F):
+// bits [0,s) -> q low, [s,2s) -> p low, [2s,F+s) -> q high, [F+s,2F) -> p high.
+HT_HD void lane_block(uint32_t b, int F, int s, uint32_t& pidx, uint32_t& qidx) {
+  const uint32_t ms = (1u << s) - 1u;
+  const uint32_t mh = (1u << (F - s)) - 1u;
+  qidx = (b & ms) | (((b >> (2 * s)) & mh) << s);
+  pidx = ((b >> s) & ms) | ((b >> (F + s)) << s);
+}
+
+// Per-group context: where each of the 2^C x 2^C tiles lives and whether it
+// is stored in the orientation the group needs (dir) or as a mirror.
+template <int C>
+struct GroupCtx {
+  uint64_t tbase[1 << C][1 << C];  // element offset of the stored tile
+  bool dir[1 << C][1 << C];
+  bool diag;
+};
+
+template <int K, int C>
+HT_HD void group_ctx(uint64_t grp, const ConjGeom<K, C>& g, GroupCtx<C>& gc) {
+  constexpr int NX = 1 << C;
+  uint32_t Ti, Tj;
+  tri_decode(grp, Ti, Tj);
+  gc.diag = (C > 0) && (Ti == Tj);
+  uint32_t TR[NX], TC[NX];
+#pragma unroll
+  for (int X = 0; X < NX; ++X) {
+    TR[X] = ins_cross<C>(Ti, (uint32_t)X, g.cpos);
+    TC[X] = ins_cross<C>(Tj, (uint32_t)X, g.cpos);
+  }
+#pragma unroll
+  for (int X = 0; X < NX; ++X) {
+#pragma unroll
+    for (int Y = 0; Y < NX; ++Y) {
+      const bool d = TR[X] >= TC[Y];
+      const uint64_t hi = d ? TR[X] : TC[Y];
+      const uint64_t lo = d ? TC[Y] : TR[X];
+      gc.dir[X][Y] = d;
+      gc.tbase[X][Y] = (tri64(hi) + lo) << (2 * g.m);
+    }
+  }
+}
+
+// Coefficients of the operation.  Form 0 (direct): the 2^k x 2^k matrix A,
+// applied as A h A^dagger.  Form 1 (transfer): the 4^k x 4^k matrix S acting
+// on the row-major vector of h.  Small sets travel by value in the kernel
+// arguments; the 16 x 16 transfer matrix of a two-qubit channel is read
+// from device memory.
+template <int K, int FORM>
+struct Coef {
+  static constexpr int D = 1 << K;
+  static constexpr int NE = FORM == 0 ? D * D : D * D * D * D;
+  double c[2 * NE];
+  HT_HD cd at(int i) const { return {c[2 * i], c[2 * i + 1]}; }
+};
+template <>
+struct Coef<2, 1> {
+  static constexpr int NE = 256;
+  const double* __restrict__ p;
+  HT_HD cd at(int i) const { return {p[2 * i], p[2 * i + 1]}; }
+};
+
+// Apply the operation to the block x (row-major, 2^k x 2^k) and hand every
+// output entry (u, v, w) to emit as soon as it is known.  The inputs stay in
+// x until the end, so emit may overwrite the entries x was loaded from.
+template <int K, int FORM, typename Emit>
+HT_HD void block_apply(const cd (&x)[(1 << K) * (1 << K)], const Coef<K, FORM>& cf, Emit&& emit) {
+  constexpr int D = 1 << K;
+  if constexpr (FORM == 0) {
+    // w = A x A^dagger, one output row at a time: t = (A x)[u, :], w[u, v] = t . conj(A[v, :])
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      cd t[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        cd acc = {0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc = cfma(acc, cf.at(u * D + l), x[l * D + j]);
+        t[j] = acc;
+      }
+#pragma unroll
+      for (int v = 0; v < D; ++v) {
+        cd acc = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc = cfma_cj(acc, t[j], cf.at(v * D + j));
+        emit(u, v, acc);
+      }
+    }
+  } else {
+    // w = S vec(x), vec row-major
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) {
+      cd acc = {0.0, 0.0};
+#pragma unroll
+      for (int f = 0; f < D * D; ++f) acc = cfma(acc, cf.at(e * D * D + f), x[f]);
+      emit(e / D, e % D, acc);
+    }
+  }
+}
+
+// Memory access of the pass: entry off of the stored tile at element offset tb.
+// The kernels use plain loads and stores; a host-side checker substitutes a
+// policy that verifies bounds and counts accesses.
+template <typename T>
+struct DirectMem {
+  typename store2<T>::type* __restrict__ h;
+  HT_HD cd load(uint64_t tb, uint32_t off) const { return load_c<T>(h + tb, off); }
+  HT_HD void store(uint64_t tb, uint32_t off, cd v) const { store_c<T>(h + tb, off, v); }
+};
+
+// Update the block with index b of the current group, in place.
+template <int K, int C, int FORM, typename Mem>
+HT_HD void conj_block(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
+                      const Coef<K, FORM>& cf, uint32_t b) {
+  constexpr int D = 1 << K;
+  constexpr int KI = K - C;
+  constexpr int IM = (1 << KI) - 1;
+  uint32_t pidx, qidx;
+  lane_block(b, g.F, g.s, pidx, qidx);
+  const uint32_t p = deposit_free<KI>(pidx, g.ipos);
+  const uint32_t q = deposit_free<KI>(qidx, g.ipos);
+  if (gc.diag && p < q) return;
+  const int m = g.m;
+
+  cd x[D * D];
+#pragma unroll
+  for (int u = 0; u < D; ++u) {
+    const uint32_t ru = p + dep_intra<KI>(u & IM, g.ipos);
+#pragma unroll
+    for (int v = 0; v < D; ++v) {
+      const uint32_t cv = q + dep_intra<KI>(v & IM, g.ipos);
+      const int X = u >> KI, Y = v >> KI;
+      const bool d = gc.dir[X][Y];
+      const uint32_t off = d ? (ru << m) + cv : (cv << m) + ru;
+      cd val = mem.load(gc.tbase[X][Y], off);
+      if (!d) val.im = -val.im;
+      x[u * D + v] = val;
+    }
+  }
+
+  block_apply<K, FORM>(x, cf, [&](int u, int v, cd w) {
+    const uint32_t ru = p + dep_intra<KI>(u & IM, g.ipos);
+    const uint32_t cv = q + dep_intra<KI>(v & IM, g.ipos);
+    const int X = u >> KI, Y = v >> KI;
+    const uint64_t tb = gc.tbase[X][Y];
+    const uint32_t offd = (ru << m) + cv;
+    const uint32_t offm = (cv << m) + ru;
+    if (!gc.diag) {
+      if (gc.dir[X][Y])
+        mem.store(tb, offd, w);
+      else
+        mem.store(tb, offm, conjg(w));
+    } else {
+      // group on the diagonal of the reduced grid: dir[X][Y] == (X >= Y)
+      if (X > Y) {
+        mem.store(tb, offd, w);
+      } else if (X < Y) {
+        if (p != q) mem.store(tb, offm, conjg(w));
+      } else {
+        mem.store(tb, offd, w);
+        if (p != q) mem.store(tb, offm, conjg(w));
+      }
+    }
+  });
+}
+
+// Geometry of a pass for an n-qubit operator with effective tile exponent m
+// and ascending targets sorted[0..K) of which the last C are cross targets.
+template <int K, int C>
+inline ConjGeom<K, C> make_geom(int n, int m, const int* sorted) {
+  ConjGeom<K, C> g{};
+  constexpr int KI = K - C;
+  g.m = m;
+  g.F = m - KI;
+  g.s = g.F < 3 ? g.F : 3;
+  for (int l = 0; l < KI; ++l) g.ipos[l] = sorted[l];
+  for (int l = 0; l < C; ++l) g.cpos[l] = sorted[KI + l] - m;
+  const uint32_t nblk = 1u << (2 * g.F);
+  g.jobs = (nblk + 63u) / 64u;
+  const uint64_t nts = (uint64_t)1 << (n - m - C);
+  g.ngroups = nts * (nts + 1) / 2;
+  return g;
+}
+
+}  // namespace ht

@@ -1,0 +1,74 @@
+// Internal interfaces between the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ht_prep.h"
+
+namespace ht {
+
+// Number of kernel classes per dtype: (k, c, form) with c <= k.
+constexpr int kClassesPerDtype = 10;
+// Class index of (k, c, form) within a dtype: k=1 -> c*2+form (0..3),
+// k=2 -> 4 + c*2 + form (4..9).
+inline int conj_class(int k, int c, int form) { return (k == 1 ? 0 : 4) + c * 2 + form; }
+
+struct LaunchTuning {
+  int block_threads = 256;  // 4 waves per workgroup
+  int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
+};
+LaunchTuning& tuning();
+
+// Enqueue one conjugation pass.  dtype 0: c128, 1: c64.  coef_dev is a device
+// buffer of >= 512 doubles that holds op.coef when the kernel reads its
+// coefficients from memory (two-qubit transfer form); the caller uploads it.
+hipError_t launch_conj(int dtype, void* buf, int n, int m, const PreparedOp& op,
+                       const double* coef_dev, int num_cu, hipStream_t s);
+
+// Elementwise and reduction kernels over the tiled storage.
+hipError_t launch_fill_zero(void* buf, size_t bytes, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_set_diag(int dtype, void* buf, int n, int m, double value, hipStream_t s);
+hipError_t launch_scale(int dtype, void* buf, uint64_t nelems, double alpha, hipStream_t s);
+hipError_t launch_pack_dense(int dtype, void* buf, int n, int m, const double* A, int64_t ld,
+                             hipStream_t s);
+hipError_t launch_unpack_dense(int dtype, const void* buf, int n, int m, double* out, int64_t ld,
+                               hipStream_t s);
+hipError_t launch_lowrank(int dtype, void* buf, int n, int m, const double* G, int rank,
+                          hipStream_t s);
+hipError_t launch_get_entries(int dtype, const void* buf, int n, int m, int64_t count,
+                              const int64_t* rows, const int64_t* cols, double* out,
+                              hipStream_t s);
+
+// Pauli strings in device form: x = bits where the string flips (X or Y),
+// z = bits with a sign (Y or Z), ny = number of Y factors mod 4.
+struct PauliTerm {
+  uint32_t x, z;
+  int32_t ny, pad;
+  double c;
+};
+// Terms sorted by x; groups[g] = {x, first term, count} for runs of equal x.
+struct PauliGroup {
+  uint32_t x, first, count, pad;
+};
+hipError_t launch_pauli_init(int dtype, void* buf, int n, int m, const PauliGroup* groups,
+                             int ngroups, const PauliTerm* terms, hipStream_t s);
+
+// Deterministic FP64 reductions; each writes one double to out_dev.
+// scratch must hold at least reduce_scratch_doubles(...) doubles.
+size_t reduce_scratch_doubles(int n, int m, int nterms);
+hipError_t launch_trace(int dtype, const void* buf, int n, int m, double* scratch, double* out_dev,
+                        hipStream_t s);
+hipError_t launch_expectation(int dtype, const void* a, const void* b, int n, int m,
+                              double* scratch, double* out_dev, hipStream_t s);
+hipError_t launch_pauli_expect(int dtype, const void* buf, int n, int m, const PauliTerm* terms,
+                               int nterms, double* scratch, double* out_dev, hipStream_t s);
+
+// Upload up to 512 doubles into a device buffer with stream-ordered kernels
+// (the values travel as kernel arguments, so no host buffer must outlive the
+// call and no pageable-memory copy is involved).
+hipError_t launch_upload(double* dst, const double* src, int count, hipStream_t s);
+
+}  // namespace ht

@@ -1,0 +1,124 @@
+"""The C-ABI boundary, checked without a GPU: the library loads, exports every
+function include/hermtile.h declares, and its pure host functions (sizes,
+per-op preparation, tuning, argument errors) behave as documented."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import layout
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hermtile.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ht_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ht():
+    import paper_2604_15765_amd as ht
+    return ht
+
+
+def test_every_declared_symbol_is_exported(ht):
+    names = declared_functions()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(ht.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_library_is_a_gfx950_hip_library(ht):
+    data = open(ht.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    assert b"conj_kernel" in data
+
+
+def test_storage_bytes(ht):
+    for n in range(1, 19):
+        for m in range(1, 9):
+            me = min(n, m)
+            N, M = 1 << n, 1 << me
+            assert ht.storage_bytes(n, m, "c128") == N * (N + M) // 2 * 16
+            assert ht.storage_bytes(n, m, "c64") == N * (N + M) // 2 * 8
+            assert ht.effective_tile_log2(n, m) == me
+            # equals the paper's padded size whenever no padding is involved
+            if n >= m:
+                assert ht.storage_bytes(n, m) == 16 * layout.tiled_elems(n, m, pad=True)
+    assert ht.storage_bytes(0, 5) == 0 and ht.storage_bytes(19, 5) == 0
+    assert ht.storage_bytes(10, 0) == 0 and ht.storage_bytes(10, 9) == 0
+    assert ht.effective_tile_log2(10, 9) == -1
+    # the headline operator: n = 16, M = 32, complex128
+    assert ht.storage_bytes(16, 5) == 34_376_515_584
+
+
+def _sorted_block_action(sorted_t, form, coef, H, n, s, s2):
+    """Apply a prepared op to the block (s, s') gathered with local bits in
+    ascending target order (Subroutine 1)."""
+    k = len(sorted_t)
+    d = 1 << k
+    r = [oracle.insert_bits(s, a, sorted_t) for a in range(d)]
+    c = [oracle.insert_bits(s2, a, sorted_t) for a in range(d)]
+    h = H[np.ix_(r, c)]
+    if form == 0:
+        return coef @ h @ coef.conj().T, r, c
+    return (coef @ h.reshape(-1)).reshape(d, d), r, c
+
+
+@pytest.mark.parametrize("picture", [0, 1])
+def test_prepare_op_reproduces_the_oracle(ht, picture):
+    """ht_prepare_op sorts targets, renumbers local bits, adjoins for the
+    Heisenberg picture and builds the row-major transfer matrix; applied to
+    blocks gathered in ascending target order it must reproduce the oracle."""
+    rng = synth.make_rng(7)
+    n = 4
+    H = synth.random_hermitian_dense(n, rng)
+    for targets in ([2], [3, 1], [1, 3], [0, 2], [2, 0]):
+        k = len(targets)
+        for r in (1, 2, 3):
+            kraus = synth.random_kraus_set(k, r, rng) * (1.0 + 0.3j)  # complex, not trace-preserving
+            st, ncross, form, coef = ht.prepare_op(n, 2, targets, kraus, picture)
+            assert st == sorted(targets)
+            assert ncross == sum(t >= 2 for t in targets)
+            assert form == (0 if r == 1 else 1)
+            ref = (oracle.kraus_map_adjoint if picture else oracle.kraus_map)(H, kraus, targets)
+            for s in range(1 << (n - k)):
+                for s2 in range(1 << (n - k)):
+                    blk, rr, cc = _sorted_block_action(st, form, coef, H, n, s, s2)
+                    assert np.allclose(blk, ref[np.ix_(rr, cc)], atol=1e-13)
+
+
+def test_prepare_op_rejects_bad_arguments(ht):
+    U = np.eye(2)
+    for bad in (dict(targets=[4]), dict(targets=[-1]), dict(targets=[1, 1], mats=np.eye(4)),
+                dict(targets=[0, 1, 2], mats=np.eye(8))):
+        t = bad.get("targets")
+        with pytest.raises(ht.HermError) as ei:
+            ht.prepare_op(4, 2, t, bad.get("mats", U))
+        assert ei.value.status == 1
+    with pytest.raises(ht.HermError):
+        ht.prepare_op(4, 2, [0], np.stack([np.eye(2)] * 5))  # r > 4^k
+    with pytest.raises(ht.HermError):
+        ht.prepare_op(4, 2, [0], U, picture=7)
+
+
+def test_tuning_validation(ht):
+    ht.set_tuning("conj_wg_per_cu", 8)
+    ht.set_tuning("conj_block_threads", 256)
+    for name, v in (("conj_wg_per_cu", 0), ("conj_block_threads", 100), ("nope", 1)):
+        with pytest.raises(ht.HermError):
+            ht.set_tuning(name, v)
+
+
+def test_kernel_class_names(ht):
+    names = ht.kernel_class_names()
+    assert len(names) == 20 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k2_c2_transfer"

@@ -1,0 +1,317 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Small operators are compared entry by entry with the dense oracle (relative
+Frobenius error <= 1e-12 in complex128).  Full-size operators (n = 14 and
+n = 16, in the launch configuration the benchmark uses) are checked on sampled
+blocks of Eq. (2) read before and after each op, plus invariants.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import layout
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ht():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_15765_amd as ht
+    return ht
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def lower_hermitian(H):
+    return np.tril(H) + np.tril(H, -1).conj().T
+
+
+def make(ht, n, m, H=None, dtype="c128"):
+    h = ht.Herm(n, m, dtype)
+    if H is not None:
+        h.init_dense(H)
+    return h
+
+
+# ----------------------------------------------------------------- storage
+
+
+@pytest.mark.parametrize("n,m", [(1, 5), (3, 2), (5, 5), (6, 2), (7, 3), (9, 5), (10, 6)])
+def test_init_dense_roundtrip_and_layout(ht, n, m):
+    rng = synth.make_rng(10 * n + m)
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H)
+    assert np.array_equal(h.to_dense(), lower_hermitian(H))
+    # raw storage is exactly the paper's tiled format (decoded independently)
+    me = ht.effective_tile_log2(n, m)
+    assert np.array_equal(h.raw_entries(), layout.encode(lower_hermitian(H), me))
+
+
+def test_init_kernels(ht):
+    rng = synth.make_rng(3)
+    n, m = 7, 3
+    h = make(ht, n, m)
+    h.init_identity(0.25)
+    assert np.array_equal(h.to_dense(), 0.25 * np.eye(1 << n))
+    h.init_zero()
+    assert not h.to_dense().any()
+    G = synth.ginibre_factor(n, 5, rng)
+    h.init_lowrank(G)
+    assert rel(h.to_dense(), G @ G.conj().T) < 1e-14
+    Gd = torch.from_numpy(G).cuda()
+    h2 = make(ht, n, m)
+    h2.init_lowrank(Gd)
+    assert rel(h2.to_dense(), G @ G.conj().T) < 1e-14
+    codes, coeffs = synth.random_pauli_sum(n, 40, rng)
+    h.init_pauli_sum(codes, coeffs)
+    assert rel(h.to_dense(), oracle.pauli_sum_matrix(codes, coeffs)) < 1e-14
+    h.scale(-2.5)
+    assert rel(h.to_dense(), -2.5 * oracle.pauli_sum_matrix(codes, coeffs)) < 1e-14
+
+
+def test_get_entries_and_copy(ht):
+    rng = synth.make_rng(4)
+    n, m = 6, 2
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H)
+    r = rng.integers(0, 1 << n, size=500)
+    c = rng.integers(0, 1 << n, size=500)
+    assert np.array_equal(h.get_entries(r, c), lower_hermitian(H)[r, c])
+    h2 = make(ht, n, m).copy_from(h)
+    assert np.array_equal(h2.to_dense(), h.to_dense())
+
+
+# ----------------------------------------------------------- single ops
+
+
+def _check_op(ht, n, m, targets, kraus, picture, rng, dtype="c128"):
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H)
+    if kraus.shape[0] == 1 and rng.random() < 0.5:
+        h.apply_unitary(targets, kraus[0], picture)
+    else:
+        h.apply_channel(targets, kraus, picture)
+    ref = (oracle.kraus_map_adjoint if picture else oracle.kraus_map)(H, kraus, targets)
+    e = rel(h.to_dense(), ref)
+    assert e <= TOL, (n, m, targets, kraus.shape[0], picture, e)
+
+
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_single_qubit_ops_every_position(ht, m):
+    rng = synth.make_rng(100 + m)
+    for n in (1, 2, 4, 6, 8):
+        for a in range(n):
+            for picture in (0, 1):
+                _check_op(ht, n, m, [a], synth.haar_unitary(2, rng)[None], picture, rng)
+                _check_op(ht, n, m, [a], synth.random_kraus_set(1, 4, rng), picture, rng)
+
+
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_two_qubit_ops_every_ordered_pair(ht, m):
+    rng = synth.make_rng(200 + m)
+    for n in (2, 3, 5, 7):
+        for a, b in itertools.permutations(range(n), 2):
+            picture = int(rng.integers(2))
+            _check_op(ht, n, m, [a, b], synth.haar_unitary(4, rng)[None], picture, rng)
+            _check_op(ht, n, m, [a, b], synth.random_kraus_set(2, int(rng.integers(2, 17)), rng),
+                      picture, rng)
+
+
+def test_complex_nonsymmetric_channels(ht):
+    """The transfer-matrix order only shows with complex non-symmetric Kraus
+    operators."""
+    rng = synth.make_rng(300)
+    S, T = synth.named_gate("S"), synth.named_gate("T")
+    ry = synth.named_gate("RY", 0.7) @ synth.named_gate("RZ", 0.3)
+    kr = np.stack([np.sqrt(0.5) * S, np.sqrt(0.3) * T, np.sqrt(0.2) * ry])
+    for m in (2, 5):
+        for a in range(8):
+            _check_op(ht, 8, m, [a], kr, 0, rng)
+
+
+def test_native_gate_exactness(ht):
+    """X twice is the identity bitwise; CNOT leaves the control-0 quarter
+    bitwise unchanged; S leaves entries with equal target bits unchanged."""
+    rng = synth.make_rng(301)
+    n, m = 8, 3
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H)
+    X = synth.named_gate("X")
+    for a in range(n):
+        h.apply_unitary([a], X)
+        h.apply_unitary([a], X)
+    assert np.array_equal(h.to_dense(), lower_hermitian(H))
+    N = 1 << n
+    idx = np.arange(N)
+    for c, t in ((1, 6), (6, 1), (0, 2), (4, 7)):
+        h.init_dense(H)
+        h.apply_unitary([c, t], synth.cnot_matrix())
+        zero = ((idx >> c) & 1) == 0
+        assert np.array_equal(h.to_dense()[np.ix_(zero, zero)], lower_hermitian(H)[np.ix_(zero, zero)])
+    for a in (0, 5):
+        h.init_dense(H)
+        h.apply_unitary([a], synth.named_gate("S"))
+        same = (((idx[:, None] ^ idx[None, :]) >> a) & 1) == 0
+        assert np.array_equal(h.to_dense()[same], lower_hermitian(H)[same])
+
+
+# --------------------------------------------------------------- circuits
+
+
+def test_plain_n8_circuit(ht):
+    """200 random ops at n = 8 (Ginibre state), whole circuit vs the dense
+    oracle, plus the reductions."""
+    G, ops = synth.circuit_plain_n8(seed=1234)
+    rho0 = oracle.density_from_factor(G)
+    for m in (3, 5):
+        h = ht.Herm(8, m)
+        h.init_lowrank(G)
+        h.scale(1.0 / h.trace())
+        for op in ops:
+            h.apply_op(op)
+        ref = oracle.apply_ops(rho0, ops)
+        assert rel(h.to_dense(), ref) <= TOL
+        assert abs(h.trace() - oracle.trace(ref)) < 1e-13
+
+
+def test_sweep_circuit_and_heisenberg_duality(ht):
+    """Every op class on every position (n = 10), then the same circuit in the
+    Heisenberg picture on a Pauli-sum observable: tr(O Phi(rho)) computed both
+    ways on the GPU agrees with the oracle."""
+    n, m = 10, 3
+    G, ops, (codes, coeffs) = synth.circuit_sweep(n=n, seed=77)
+    rho0 = oracle.density_from_factor(G)
+    rho = ht.Herm(n, m)
+    rho.init_lowrank(G)
+    rho.scale(1.0 / rho.trace())
+    for op in ops:
+        rho.apply_op(op)
+    ref = oracle.apply_ops_local(rho0, ops)
+    assert rel(rho.to_dense(), ref) <= TOL
+    O = ht.Herm(n, m).init_pauli_sum(codes, coeffs)
+    for op in reversed(ops):
+        O.apply_op(op, ht.HEISENBERG)
+    O_ref = oracle.apply_ops_local(oracle.pauli_sum_matrix(codes, coeffs), list(reversed(ops)), adjoint=True)
+    assert rel(O.to_dense(), O_ref) <= TOL
+    rho_init = ht.Herm(n, m)
+    rho_init.init_lowrank(G)
+    rho_init.scale(1.0 / rho_init.trace())
+    want = oracle.pauli_sum_expectation(ref, codes, coeffs)
+    got_s = rho.expectation_pauli_sum(codes, coeffs)
+    got_h = O.expectation(rho_init)
+    assert abs(got_s - want) < 1e-12 * max(1.0, abs(want))
+    assert abs(got_h - want) < 1e-12 * max(1.0, abs(want))
+
+
+# ------------------------------------------------------------- reductions
+
+
+def test_reductions_against_oracle(ht):
+    rng = synth.make_rng(400)
+    for n, m in ((3, 5), (6, 2), (9, 4)):
+        A = synth.random_hermitian_dense(n, rng)
+        B = synth.random_hermitian_dense(n, rng)
+        a, b = make(ht, n, m, A), make(ht, n, m, B)
+        assert abs(a.trace() - oracle.trace(A)) < 1e-12 * (1 << n)
+        assert abs(a.expectation(b) - oracle.expectation(A, B)) < 1e-12 * np.linalg.norm(A) * np.linalg.norm(B)
+        codes, coeffs = synth.random_pauli_sum(n, 30, rng)
+        want = oracle.pauli_sum_expectation(A, codes, coeffs)
+        assert abs(a.expectation_pauli_sum(codes, coeffs) - want) < 1e-12 * np.linalg.norm(A) * np.abs(coeffs).sum()
+        # deterministic: identical bits on repetition
+        assert a.trace() == a.trace() and a.expectation(b) == a.expectation(b)
+
+
+# ------------------------------------------------------------- errors
+
+
+def test_invalid_arguments_leave_state_untouched(ht):
+    rng = synth.make_rng(500)
+    n, m = 5, 2
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H)
+    U = synth.haar_unitary(2, rng)
+    for t in ([5], [-1]):
+        with pytest.raises(ht.HermError):
+            h.apply_unitary(t, U)
+    with pytest.raises(ht.HermError):
+        h.apply_unitary([1, 1], synth.haar_unitary(4, rng))
+    with pytest.raises(ht.HermError):
+        h.apply_channel([0], np.stack([U] * 5))
+    with pytest.raises(ht.HermError):
+        h.expectation(make(ht, 6, 2))
+    assert np.array_equal(h.to_dense(), lower_hermitian(H))
+
+
+def test_borrowed_buffer_survives_destroy(ht):
+    h = ht.Herm(6, 3)
+    buf = h.buffer
+    h.init_identity(1.0)
+    h.close()
+    buf.fill_(7)
+    torch.cuda.synchronize()
+    assert int(buf[0].item()) == 7
+
+
+# --------------------------------------------------------- full sizes
+
+
+def _sampled_blocks(n, targets, nblocks, rng):
+    k = len(targets)
+    s = rng.integers(0, 1 << (n - k), size=nblocks)
+    s2 = rng.integers(0, 1 << (n - k), size=nblocks)
+    rows = np.stack([oracle.block_indices(int(x), targets) for x in s])
+    cols = np.stack([oracle.block_indices(int(x), targets) for x in s2])
+    d = 1 << k
+    R = np.repeat(rows[:, :, None], d, axis=2).reshape(nblocks, -1)
+    C = np.repeat(cols[:, None, :], d, axis=1).reshape(nblocks, -1)
+    return R.reshape(-1), C.reshape(-1), d
+
+
+def _sampled_op_check(h, op, picture, n, rng, nblocks=1500):
+    R, C, d = _sampled_blocks(n, op.targets, nblocks, rng)
+    before = h.get_entries(R, C).reshape(nblocks, d, d)
+    h.apply_op(op, picture)
+    after = h.get_entries(R, C).reshape(nblocks, d, d)
+    want = oracle.block_update(before, op.mats, adjoint=bool(picture))
+    return rel(after, want)
+
+
+@pytest.mark.parametrize("n", [14, 16])
+def test_full_size_sampled_blocks(ht, n):
+    """Full-size operators (n = 14: 2.15 GB, n = 16: 34.4 GB of c128 tiles,
+    tile edge 32, the benchmark's launch configuration): every op class at
+    intra and cross positions, checked on 1500 sampled blocks per op, plus
+    trace preservation over the whole operator."""
+    rng = synth.make_rng(900 + n)
+    G = synth.ginibre_factor(n, 16, rng)
+    h = ht.Herm(n, 5)
+    h.init_lowrank(G)
+    h.scale(1.0 / h.trace())
+    ops = [
+        synth.random_ops.unitary_op([2], synth.haar_unitary(2, rng)),                 # k=1 c=0
+        synth.random_ops.unitary_op([n - 1], synth.haar_unitary(2, rng)),             # k=1 c=1 (top)
+        synth.random_ops.unitary_op([5], synth.haar_unitary(2, rng)),                 # k=1 c=1 (lowest cross)
+        synth.random_ops.channel_op([9], synth.depolarising_kraus(0.07)),
+        synth.random_ops.channel_op([3], synth.amplitude_damping_kraus(0.05)),
+        synth.random_ops.unitary_op([1, 3], synth.haar_unitary(4, rng)),             # k=2 c=0
+        synth.random_ops.unitary_op([4, 5], synth.haar_unitary(4, rng)),             # k=2 c=1
+        synth.random_ops.unitary_op([n - 1, 6], synth.haar_unitary(4, rng)),         # k=2 c=2
+        synth.random_ops.channel_op([7, 12], synth.random_kraus_set(2, 3, rng)),     # k=2 c=2 transfer
+        synth.random_ops.unitary_op([0, n - 2], synth.cnot_matrix()),                # k=2 c=1
+    ]
+    for i, op in enumerate(ops):
+        pic = i % 2 if op.kind == "unitary" else 0
+        e = _sampled_op_check(h, op, pic, n, rng)
+        assert e <= TOL, (op.label, op.targets, e)
+    assert abs(h.trace() - 1.0) < 1e-12
