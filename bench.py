@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-n", type=int, default=12,
                    help="qubits of the dense sub-operator the CPU oracle is timed on")
+    p.add_argument("--tune", action="append", default=[], metavar="NAME=VALUE",
+                   help="launch tuning passed to ht_set_tuning (repeatable)")
     p.add_argument("--copy-only", action="store_true",
                    help="only run the plain copy kernel on a buffer of the operator's size "
                         "(calibration of hardware byte counters)")
@@ -111,6 +113,11 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     n, m = args.n, args.tile_log2
+    tuning = {}
+    for t in args.tune:
+        name, value = t.split("=")
+        ht.set_tuning(name, int(value))
+        tuning[name] = int(value)
 
     if args.copy_only:
         a = ht.Herm(n, m, args.dtype)
@@ -192,7 +199,7 @@ def main():
                          f"{1 << h.tile_log2}, per step one layer (Haar U(2) on all qubits, brickwork "
                          f"Haar U(4), amplitude damping 0.01 on all qubits) + trace + 64-term Pauli sum"),
             "n": n, "tile_edge": 1 << h.tile_log2, "storage": args.dtype,
-            "ops_per_step": nops / args.steps, "storage_bytes": h.nbytes,
+            "ops_per_step": nops / args.steps, "storage_bytes": h.nbytes, "tuning": tuning,
         },
         "hbm_GBps": nops * per_op_bytes / elapsed / 1e9,
         "hbm_frac": nops * per_op_bytes / elapsed / 1e9 / HBM_PEAK_GBPS,

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hermtile.h"
+#include "hermtile.h"
 #include "ht_internal.h"
 #include "ht_prep.h"
 
@@ -617,6 +617,16 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     if (value != 64 && value != 128 && value != 256)
       return fail(HT_EINVAL, "conj_block_threads must be 64, 128 or 256");
     ht::tuning().block_threads = (int)value;
+    return HT_OK;
+  }
+  if (k == "conj_order") {
+    if (value < 0 || value > 1) return fail(HT_EINVAL, "conj_order must be 0 or 1");
+    ht::tuning().order = (int)value;
+    return HT_OK;
+  }
+  if (k == "conj_mem_mode") {
+    if (value < 0 || value > 3) return fail(HT_EINVAL, "conj_mem_mode must be in [0, 3]");
+    ht::tuning().mem_mode = (int)value;
     return HT_OK;
   }
   return fail(HT_EINVAL, "unknown tuning parameter '%s'", name);

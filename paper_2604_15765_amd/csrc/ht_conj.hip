@@ -21,23 +21,34 @@ LaunchTuning& tuning() {
   return t;
 }
 
-template <typename T, int K, int C, int FORM>
+template <typename T, int K, int C, int FORM, int MODE>
 __global__ void __launch_bounds__(256)
     conj_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
-                const double* __restrict__ coef) {
+                const double* __restrict__ coef, int order) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  const uint32_t nblk = 1u << (2 * g.F);
-  const DirectMem<T> mem{h};
+  const DirectMem<T, MODE> mem{h};
   if constexpr (K == 2 && FORM == 1) cf.p = coef;  // 16 x 16 transfer matrix, read-only
-  for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
-    GroupCtx<C> gc;
-    group_ctx<K, C>(grp, g, gc);
-    for (uint32_t job = 0; job < g.jobs; ++job) {
-      const uint32_t b = job * 64u + lane;
-      if (b < nblk) conj_block<K, C, FORM>(mem, g, gc, cf, b);
+  constexpr int JU = conj_unroll(K);
+  if (order == 0) {
+    // one wave walks all patches of a group
+    for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
+      GroupCtx<C> gc;
+      group_ctx<K, C>(grp, g, gc);
+      conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane);
+    }
+  } else {
+    // (group, step of JU patches) items: neighbouring waves sweep one group
+    const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
+    const int sl = 31 - __builtin_clz(steps);
+    const uint64_t items = g.ngroups << sl;
+    for (uint64_t it = wave; it < items; it += nwaves) {
+      GroupCtx<C> gc;
+      group_ctx<K, C>(it >> sl, g, gc);
+      const uint32_t j0 = (uint32_t)(it & (steps - 1)) * JU;
+      conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane, j0, j0 + JU);
     }
   }
 }
@@ -54,12 +65,30 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   }
   const int threads = tuning().block_threads;
   const uint64_t waves_per_wg = (uint64_t)threads / 64;
-  uint64_t wgs = (g.ngroups + waves_per_wg - 1) / waves_per_wg;
+  const uint64_t steps = (g.jobs + conj_unroll(K) - 1) / conj_unroll(K);
+  const uint64_t items = tuning().order == 0 ? g.ngroups : g.ngroups * steps;
+  uint64_t wgs = (items + waves_per_wg - 1) / waves_per_wg;
   const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
-  hipLaunchKernelGGL((conj_kernel<T, K, C, FORM>), dim3((unsigned)wgs), dim3(threads), 0, s,
-                     reinterpret_cast<typename store2<T>::type*>(buf), g, cf, coef_dev);
+  auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
+  switch (tuning().mem_mode) {
+    case 1:
+      hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 1>), dim3((unsigned)wgs), dim3(threads), 0, s,
+                         hp, g, cf, coef_dev, tuning().order);
+      break;
+    case 2:
+      hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 2>), dim3((unsigned)wgs), dim3(threads), 0, s,
+                         hp, g, cf, coef_dev, tuning().order);
+      break;
+    case 3:
+      hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 3>), dim3((unsigned)wgs), dim3(threads), 0, s,
+                         hp, g, cf, coef_dev, tuning().order);
+      break;
+    default:
+      hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 0>), dim3((unsigned)wgs), dim3(threads), 0, s,
+                         hp, g, cf, coef_dev, tuning().order);
+  }
   return hipGetLastError();
 }
 

@@ -155,11 +155,23 @@ struct GroupCtx {
   bool diag;
 };
 
+// A value every lane of a wave holds identically: on the GPU, tell the
+// compiler so (it then keeps it in scalar registers).
+HT_HD uint32_t wave_uniform(uint32_t x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_readfirstlane(x);
+#else
+  return x;
+#endif
+}
+
 template <int K, int C>
 HT_HD void group_ctx(uint64_t grp, const ConjGeom<K, C>& g, GroupCtx<C>& gc) {
   constexpr int NX = 1 << C;
   uint32_t Ti, Tj;
   tri_decode(grp, Ti, Tj);
+  Ti = wave_uniform(Ti);  // grp is the same on every lane of the wave
+  Tj = wave_uniform(Tj);
   gc.diag = (C > 0) && (Ti == Tj);
   uint32_t TR[NX], TC[NX];
 #pragma unroll
@@ -240,34 +252,82 @@ HT_HD void block_apply(const cd (&x)[(1 << K) * (1 << K)], const Coef<K, FORM>& 
 // Memory access of the pass: entry off of the stored tile at element offset tb.
 // The kernels use plain loads and stores; a host-side checker substitutes a
 // policy that verifies bounds and counts accesses.
+// MODE bit 0: loads carry the nontemporal hint; bit 1: stores do.
 template <typename T>
-struct DirectMem {
-  typename store2<T>::type* __restrict__ h;
-  HT_HD cd load(uint64_t tb, uint32_t off) const { return load_c<T>(h + tb, off); }
-  HT_HD void store(uint64_t tb, uint32_t off, cd v) const { store_c<T>(h + tb, off, v); }
+struct native2;
+template <>
+struct native2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct native2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
 };
 
-// Update the block with index b of the current group, in place.
-template <int K, int C, int FORM, typename Mem>
-HT_HD void conj_block(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
-                      const Coef<K, FORM>& cf, uint32_t b) {
+template <typename T, int MODE = 0>
+struct DirectMem {
+  typename store2<T>::type* __restrict__ h;
+  using V = typename native2<T>::type;
+  // tile base (uniform) plus a 32-bit byte offset inside the tile
+  HT_HD const V* at(uint64_t tb, uint32_t off) const {
+    return reinterpret_cast<const V*>(reinterpret_cast<const char*>(h + tb) +
+                                      (uint32_t)(off * (uint32_t)sizeof(V)));
+  }
+  HT_HD cd load(uint64_t tb, uint32_t off) const {
+    V v;
+    if constexpr ((MODE & 1) != 0)
+      v = __builtin_nontemporal_load(at(tb, off));
+    else
+      v = *at(tb, off);
+    return {(double)v.x, (double)v.y};
+  }
+  HT_HD void store(uint64_t tb, uint32_t off, cd w) const {
+    V v;
+    v.x = (T)w.re;
+    v.y = (T)w.im;
+    V* p = const_cast<V*>(at(tb, off));
+    if constexpr ((MODE & 2) != 0)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
+  }
+};
+
+// Where block b of the current group sits: base row p and base column q
+// inside a tile; inactive for the skipped half of diagonal groups and for
+// padding lanes.
+struct BlockPos {
+  uint32_t p, q;
+  bool active;
+};
+
+template <int K, int C>
+HT_HD BlockPos block_pos(const ConjGeom<K, C>& g, const GroupCtx<C>& gc, uint32_t b, bool valid) {
+  constexpr int KI = K - C;
+  uint32_t pidx, qidx;
+  lane_block(b, g.F, g.s, pidx, qidx);
+  BlockPos r;
+  r.p = deposit_free<KI>(pidx, g.ipos);
+  r.q = deposit_free<KI>(qidx, g.ipos);
+  r.active = valid && !(gc.diag && r.p < r.q);
+  return r;
+}
+
+// Read the block's 2^k x 2^k entries (row-major, local bits in ascending
+// target order); mirrored tiles are read transposed and conjugated.
+template <int K, int C, typename Mem>
+HT_HD void block_load(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
+                      const BlockPos& bp, cd (&x)[(1 << K) * (1 << K)]) {
   constexpr int D = 1 << K;
   constexpr int KI = K - C;
   constexpr int IM = (1 << KI) - 1;
-  uint32_t pidx, qidx;
-  lane_block(b, g.F, g.s, pidx, qidx);
-  const uint32_t p = deposit_free<KI>(pidx, g.ipos);
-  const uint32_t q = deposit_free<KI>(qidx, g.ipos);
-  if (gc.diag && p < q) return;
   const int m = g.m;
-
-  cd x[D * D];
 #pragma unroll
   for (int u = 0; u < D; ++u) {
-    const uint32_t ru = p + dep_intra<KI>(u & IM, g.ipos);
+    const uint32_t ru = bp.p + dep_intra<KI>(u & IM, g.ipos);
 #pragma unroll
     for (int v = 0; v < D; ++v) {
-      const uint32_t cv = q + dep_intra<KI>(v & IM, g.ipos);
+      const uint32_t cv = bp.q + dep_intra<KI>(v & IM, g.ipos);
       const int X = u >> KI, Y = v >> KI;
       const bool d = gc.dir[X][Y];
       const uint32_t off = d ? (ru << m) + cv : (cv << m) + ru;
@@ -276,7 +336,17 @@ HT_HD void conj_block(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>
       x[u * D + v] = val;
     }
   }
+}
 
+// Apply the operation to the loaded block and write the results back.
+template <int K, int C, int FORM, typename Mem>
+HT_HD void block_update_store(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
+                              const Coef<K, FORM>& cf, const BlockPos& bp,
+                              const cd (&x)[(1 << K) * (1 << K)]) {
+  constexpr int KI = K - C;
+  constexpr int IM = (1 << KI) - 1;
+  const int m = g.m;
+  const uint32_t p = bp.p, q = bp.q;
   block_apply<K, FORM>(x, cf, [&](int u, int v, cd w) {
     const uint32_t ru = p + dep_intra<KI>(u & IM, g.ipos);
     const uint32_t cv = q + dep_intra<KI>(v & IM, g.ipos);
@@ -301,6 +371,36 @@ HT_HD void conj_block(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>
       }
     }
   });
+}
+
+// Blocks in flight per lane: 16 entry loads for k = 1 (4 blocks) and for
+// k = 2 (one block) -- the depth at which an in-place stream on MI355X
+// reaches its best bandwidth.
+constexpr int conj_unroll(int K) { return K == 1 ? 4 : 1; }
+
+// All blocks one lane owns in the current group: patches of 64 blocks, JU
+// patches per step, every load of a step issued before any update (JU
+// blocks in flight per lane).
+template <int JU, int K, int C, int FORM, typename Mem>
+HT_HD void conj_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
+                           const Coef<K, FORM>& cf, uint32_t lane, uint32_t job_begin = 0,
+                           uint32_t job_end = 0xffffffffu) {
+  constexpr int D = 1 << K;
+  const uint32_t nblk = 1u << (2 * g.F);
+  if (job_end > g.jobs) job_end = g.jobs;
+  for (uint32_t job = job_begin; job < job_end; job += JU) {
+    BlockPos bp[JU];
+    cd x[JU][D * D];
+#pragma unroll
+    for (int j = 0; j < JU; ++j) {
+      const uint32_t b = (job + j) * 64u + lane;
+      bp[j] = block_pos<K, C>(g, gc, b, job + j < job_end && b < nblk);
+      if (bp[j].active) block_load<K, C>(mem, g, gc, bp[j], x[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < JU; ++j)
+      if (bp[j].active) block_update_store<K, C, FORM>(mem, g, gc, cf, bp[j], x[j]);
+  }
 }
 
 // Geometry of a pass for an n-qubit operator with effective tile exponent m

@@ -1,6 +1,6 @@
 // Host-side check of the conjugation pass's indexing (test support only; the
 // library never loads this).  It runs the same per-lane body the GPU kernel
-// runs (conj_block from ht_geom.h) for every group, patch and lane of a pass,
+// runs (conj_group_lane from ht_geom.h) for every group and lane of a pass,
 // sequentially on a host copy of the tiled storage, with a memory policy that
 // rejects out-of-range accesses and counts reads and writes per entry.  Blocks
 // of one pass touch disjoint entries, so the sequential order gives the same
@@ -40,8 +40,9 @@ struct CheckedMem {
   }
 };
 
-template <int K, int C, int FORM>
-void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, uint64_t* lanes_run) {
+template <int JU, int K, int C, int FORM>
+void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int order,
+         uint64_t* lanes_run) {
   ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, op.sorted);
   ht::Coef<K, FORM> cf;
   if constexpr (K == 2 && FORM == 1) {
@@ -49,18 +50,18 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, uint64_t
   } else {
     for (int i = 0; i < 2 * ht::Coef<K, FORM>::NE; ++i) cf.c[i] = op.coef[i];
   }
-  const uint32_t nblk = 1u << (2 * g.F);
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
     ht::GroupCtx<C> gc;
     ht::group_ctx<K, C>(grp, g, gc);
-    for (uint32_t job = 0; job < g.jobs; ++job)
-      for (uint32_t lane = 0; lane < 64; ++lane) {
-        const uint32_t b = job * 64u + lane;
-        if (b < nblk) {
-          ht::conj_block<K, C, FORM>(mem, g, gc, cf, b);
-          ++*lanes_run;
-        }
+    for (uint32_t lane = 0; lane < 64; ++lane) {
+      if (order == 0) {
+        ht::conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane);
+      } else {  // the per-step job ranges of the flattened work order
+        for (uint32_t j0 = 0; j0 < g.jobs; j0 += JU)
+          ht::conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane, j0, j0 + JU);
       }
+      ++*lanes_run;
+    }
   }
 }
 
@@ -70,19 +71,22 @@ extern "C" {
 
 // raw: host c128 tiled storage of nelems entries (2*nelems doubles), updated
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
-// caller, or NULL.  Returns 0 on success, 1 on invalid op, 2 on an
+// caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
+// ranges of the flattened work order.  Returns 0 on success, 1 on invalid op, 2 on an
 // out-of-range access.  *lanes_run receives the number of lane bodies run.
 int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, const int* targets,
                      int r, const double* kraus, int heisenberg, int32_t* write_counts,
-                     int32_t* read_counts, uint64_t* lanes_run, char* err, size_t errlen) {
+                     int32_t* read_counts, uint64_t* lanes_run, int order, char* err,
+                     size_t errlen) {
   const int m = tile_log2 < n ? tile_log2 : n;
   ht::PreparedOp op;
   if (ht::prepare_op(n, m, k, targets, r, kraus, heisenberg, &op, err, errlen) != 0) return 1;
   bool oob = false;
   CheckedMem mem{reinterpret_cast<double2*>(raw), nelems, write_counts, read_counts, &oob};
   uint64_t lanes = 0;
-#define HT_CASE(K_, C_, F_) \
-  if (op.k == K_ && op.ncross == C_ && op.form == F_) run<K_, C_, F_>(mem, n, m, op, &lanes);
+#define HT_CASE(K_, C_, F_)                                 \
+  if (op.k == K_ && op.ncross == C_ && op.form == F_)       \
+    run<ht::conj_unroll(K_), K_, C_, F_>(mem, n, m, op, order, &lanes);
   HT_CASE(1, 0, 0)
   HT_CASE(1, 0, 1)
   HT_CASE(1, 1, 0)

@@ -315,3 +315,52 @@ def test_full_size_sampled_blocks(ht, n):
         e = _sampled_op_check(h, op, pic, n, rng)
         assert e <= TOL, (op.label, op.targets, e)
     assert abs(h.trace() - 1.0) < 1e-12
+
+
+# ------------------------------------------------------------- complex64
+
+C64_EPS = 2.0 ** -24  # unit roundoff of float32 (round to nearest)
+
+
+def quantise_c64(H):
+    return H.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("m", [2, 5])
+def test_c64_single_ops_within_one_rounding(ht, m):
+    """complex64 storage, FP64 arithmetic: one pass rounds each FP64 result
+    to float32 once, so against the oracle applied to the same stored input
+    the relative Frobenius error is at most 2^-24 (checked with margin 2)."""
+    rng = synth.make_rng(700 + m)
+    n = 7
+    for targets in ([0], [4], [6], [1, 2], [5, 1], [3, 6], [6, 5]):
+        k = len(targets)
+        for kraus in (synth.haar_unitary(1 << k, rng)[None], synth.random_kraus_set(k, 3, rng)):
+            H = synth.random_hermitian_dense(n, rng)
+            h = make(ht, n, m, H, dtype="c64")
+            Hq = lower_hermitian(quantise_c64(H))
+            assert np.array_equal(h.to_dense(), Hq)
+            h.apply_channel(targets, kraus)
+            e = rel(h.to_dense(), oracle.kraus_map(Hq, kraus, targets))
+            assert e <= 2 * C64_EPS, (targets, kraus.shape[0], e)
+
+
+def test_c64_circuit_error_bound_and_fp64_reductions(ht):
+    """The n = 8 circuit in complex64 storage: error vs the FP64 oracle stays
+    within (passes + 1) * 2^-24 relative (one rounding per pass plus the
+    input), and trace / Pauli-sum reductions accumulate in FP64."""
+    G, ops = synth.circuit_plain_n8(seed=1234)
+    rho0 = oracle.density_from_factor(G)
+    h = ht.Herm(8, 5, "c64")
+    h.init_lowrank(G)
+    h.scale(1.0 / h.trace())
+    for op in ops:
+        h.apply_op(op)
+    ref = oracle.apply_ops(rho0, ops)
+    e = rel(h.to_dense(), ref)
+    assert e <= (len(ops) + 1) * C64_EPS, e
+    # reductions of the stored (float) entries are exact to FP64 rounding
+    D = h.to_dense()
+    assert abs(h.trace() - float(np.real(np.trace(D)))) < 1e-13
+    codes, coeffs = synth.random_pauli_sum(8, 32, synth.make_rng(5))
+    assert abs(h.expectation_pauli_sum(codes, coeffs) - oracle.pauli_sum_expectation(D, codes, coeffs)) < 1e-12

@@ -1,6 +1,6 @@
 """The conjugation pass's per-lane body, run on the CPU, against the oracle.
 
-``_hostcheck.so`` compiles the same ``conj_block`` the GPU kernel runs (from
+``_hostcheck.so`` compiles the same ``conj_group_lane`` the GPU kernel runs (from
 csrc/ht_geom.h) for the host and drives it over every group, patch and lane
 of a pass with a memory policy that rejects out-of-range accesses and counts
 writes.  These tests establish, before anything runs on a GPU, that every
@@ -33,12 +33,13 @@ def hc():
     f = lib.htc_emulate_conj
     vp = ctypes.c_void_p
     f.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp,
-                  ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_char_p, ctypes.c_size_t]
+                  ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_char_p,
+                  ctypes.c_size_t]
     f.restype = ctypes.c_int
     return f
 
 
-def emulate(f, raw, n, m, targets, kraus, heis):
+def emulate(f, raw, n, m, targets, kraus, heis, order=0):
     raw = np.ascontiguousarray(raw, dtype=np.complex128).copy()
     kraus = np.ascontiguousarray(kraus, dtype=np.complex128)
     t = np.ascontiguousarray(targets, dtype=np.int32)
@@ -46,7 +47,7 @@ def emulate(f, raw, n, m, targets, kraus, heis):
     lanes = ctypes.c_uint64()
     err = ctypes.create_string_buffer(256)
     rc = f(raw.ctypes.data, raw.size, n, m, len(targets), t.ctypes.data, kraus.shape[0], kraus.ctypes.data,
-           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), err, 256)
+           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, err, 256)
     assert rc == 0, err.value.decode()
     return raw, wc
 
@@ -62,7 +63,8 @@ def rel(a, b):
 def check(f, n, m, targets, kraus, heis, rng):
     H = synth.random_hermitian_dense(n, rng)
     raw = layout.encode(H, m)
-    out, wc = emulate(f, raw, n, m, targets, kraus, heis)
+    order = int(rng.integers(2))  # both work orders of the kernel
+    out, wc = emulate(f, raw, n, m, targets, kraus, heis, order)
     assert np.all(wc == 1), f"write counts {np.unique(wc)} for n={n} m={m} t={targets}"
     got = layout.decode(out, n, m)
     ref = reference(H, kraus, targets, heis)
