@@ -203,6 +203,60 @@ ht_status ht_expectation_pauli_sum(const ht_herm* h, int nterms, const uint8_t* 
 /* H = alpha * H (for example alpha = 1 / tr H to normalise). */
 ht_status ht_scale(ht_herm* h, double alpha);
 
+/* ------------------------------------------------------------- batches -- */
+
+/* A batch queues k-local operations for many independent operators and runs
+ * them all in ONE persistent launch (the conjugation pass of Section III-C,
+ * applied per operator in the order queued).  Each workgroup of the launch
+ * takes operators from a queue (largest work first) and runs an operator's
+ * whole sequence, with a barrier between consecutive ops; an operator whose
+ * storage fits the LDS budget is evolved in LDS and written back once.
+ * Results are bitwise identical to applying the same ops one call at a time.
+ * Operators must live on one device; a batch may mix c128 and c64 operators
+ * (one launch per storage type).  Not thread-safe. */
+typedef struct ht_batch ht_batch;
+
+ht_status ht_batch_create(ht_batch** out);
+/* Waits for the batch's last run and frees its tables.  Accepts NULL. */
+ht_status ht_batch_destroy(ht_batch* b);
+
+/* Schedule parameters: "threads" (64..1024, power of two, default 256) per
+ * workgroup; "wg_per_cu" (1..32, default 2) workgroups per compute unit;
+ * "lds_max_bytes" (0..163840, default 65536): operators up to this size run
+ * in LDS (0 disables LDS staging).  HT_EINVAL for an unknown name or value. */
+ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value);
+
+/* Queue one op for operator h; arguments as ht_apply_unitary /
+ * ht_apply_channel.  The matrices are prepared and copied before return.
+ * h must stay alive until the run that executes the op has finished. */
+ht_status ht_batch_add_unitary(ht_batch* b, ht_herm* h, int k, const int* targets, const double* U,
+                               ht_picture picture);
+ht_status ht_batch_add_channel(ht_batch* b, ht_herm* h, int k, const int* targets, int r,
+                               const double* kraus, ht_picture picture);
+
+/* Number of operators and of ops queued (either pointer may be NULL). */
+ht_status ht_batch_size(const ht_batch* b, int64_t* noperators, int64_t* nops);
+
+/* Enqueue every queued op on hip_stream (one launch per storage type) and
+ * return.  Work already enqueued on the operators' own streams is waited for
+ * first.  The queue is kept: ht_batch_clear empties it. */
+ht_status ht_batch_run(ht_batch* b, void* hip_stream);
+ht_status ht_batch_clear(ht_batch* b);
+
+/* --------------------------------------------------------------- graphs -- */
+
+/* Capture hot-path calls into a HIP graph and replay them with one launch.
+ * Between ht_capture_begin(s) and ht_capture_end(s, &g), calls of handles
+ * whose stream is s are recorded instead of executed (set the stream with
+ * ht_herm_set_stream before beginning; reductions, init and IO calls must
+ * not be made while capturing).  ht_graph_launch replays the recorded ops on
+ * the same operators.  s must not be the null stream. */
+typedef struct ht_graph ht_graph;
+ht_status ht_capture_begin(void* hip_stream);
+ht_status ht_capture_end(void* hip_stream, ht_graph** out);
+ht_status ht_graph_launch(ht_graph* g, void* hip_stream);
+ht_status ht_graph_destroy(ht_graph* g);
+
 /* --------------------------------------------------------- diagnostics -- */
 
 /* Message describing the last error on the calling thread ("" if none). */

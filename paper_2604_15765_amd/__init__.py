@@ -16,8 +16,9 @@ from typing import Optional, Sequence
 import numpy as np
 import torch  # first: the library must bind to the HIP runtime torch has loaded
 
-__all__ = ["Herm", "lib", "SCHRODINGER", "HEISENBERG", "HermError", "storage_bytes",
-           "effective_tile_log2", "prepare_op", "kernel_class_names", "set_tuning"]
+__all__ = ["Herm", "Batch", "Graph", "capture_begin", "capture_end", "lib", "SCHRODINGER",
+           "HEISENBERG", "HermError", "storage_bytes", "effective_tile_log2", "prepare_op",
+           "kernel_class_names", "set_tuning"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhermtile.so")
@@ -87,6 +88,18 @@ def _load():
         "ht_kernel_class_name": (ctypes.c_char_p, [c_int]),
         "ht_prepare_op": (c_int, [c_int, c_int, c_int, vp, c_int, vp, c_int, vp, P(c_int), P(c_int), vp]),
         "ht_set_tuning": (c_int, [ctypes.c_char_p, c_int64]),
+        "ht_batch_create": (c_int, [P(vp)]),
+        "ht_batch_destroy": (c_int, [vp]),
+        "ht_batch_set_param": (c_int, [vp, ctypes.c_char_p, c_int64]),
+        "ht_batch_add_unitary": (c_int, [vp, vp, c_int, vp, vp, c_int]),
+        "ht_batch_add_channel": (c_int, [vp, vp, c_int, vp, c_int, vp, c_int]),
+        "ht_batch_size": (c_int, [vp, P(c_int64), P(c_int64)]),
+        "ht_batch_run": (c_int, [vp, vp]),
+        "ht_batch_clear": (c_int, [vp]),
+        "ht_capture_begin": (c_int, [vp]),
+        "ht_capture_end": (c_int, [vp, P(vp)]),
+        "ht_graph_launch": (c_int, [vp, vp]),
+        "ht_graph_destroy": (c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -337,3 +350,99 @@ class Herm:
         names = kernel_class_names()
         return {names[i]: dict(launches=int(launches[i]), ms=float(ms[i]), bytes=float(by[i]))
                 for i in range(nc.value) if launches[i] > 0}
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Batch:
+    """ht_batch: ops for many operators, executed in one persistent launch."""
+
+    def __init__(self, **params):
+        b = ctypes.c_void_p()
+        _check(lib.ht_batch_create(ctypes.byref(b)))
+        self._b = b
+        self._keep = {}
+        for k, v in params.items():
+            self.set_param(k, v)
+
+    def set_param(self, name: str, value: int) -> None:
+        _check(lib.ht_batch_set_param(self._b, name.encode(), int(value)))
+
+    def add_unitary(self, h: Herm, targets, U, picture: int = SCHRODINGER) -> None:
+        U = _c128(U)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_batch_add_unitary(self._b, h.handle, len(targets), _ptr(t), _ptr(U), picture))
+        self._keep[id(h)] = h
+
+    def add_channel(self, h: Herm, targets, kraus, picture: int = SCHRODINGER) -> None:
+        K = _c128(kraus)
+        if K.ndim == 2:
+            K = K[None]
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_batch_add_channel(self._b, h.handle, len(targets), _ptr(t), K.shape[0], _ptr(K),
+                                        picture))
+        self._keep[id(h)] = h
+
+    def add_op(self, h: Herm, op, picture: int = SCHRODINGER) -> None:
+        if op.kind == "unitary":
+            self.add_unitary(h, op.targets, op.mats[0], picture)
+        else:
+            self.add_channel(h, op.targets, op.mats, picture)
+
+    def size(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.ht_batch_size(self._b, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def run(self, stream=None) -> None:
+        _check(lib.ht_batch_run(self._b, _stream_ptr(stream)))
+
+    def clear(self) -> None:
+        _check(lib.ht_batch_clear(self._b))
+        self._keep = {}
+
+    def close(self) -> None:
+        if getattr(self, "_b", None):
+            _check(lib.ht_batch_destroy(self._b))
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """ht_graph: a captured sequence of hot-path calls."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._g = handle
+
+    def launch(self, stream=None) -> None:
+        _check(lib.ht_graph_launch(self._g, _stream_ptr(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_g", None):
+            _check(lib.ht_graph_destroy(self._g))
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture_begin(stream) -> None:
+    _check(lib.ht_capture_begin(_stream_ptr(stream)))
+
+
+def capture_end(stream) -> Graph:
+    g = ctypes.c_void_p()
+    _check(lib.ht_capture_end(_stream_ptr(stream), ctypes.byref(g)))
+    return Graph(g)

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hermtile.h"
+#include "ht_handle.h"
 #include "ht_internal.h"
 #include "ht_prep.h"
 
@@ -16,7 +17,16 @@ namespace {
 
 thread_local std::string g_err;
 
-ht_status fail(ht_status st, const char* fmt, ...) {
+size_t elem_bytes(int dtype) { return dtype == HT_C128 ? 16 : 8; }
+
+uint64_t stored_elems(int n, int m) {
+  const uint64_t N = 1ull << n, M = 1ull << m;
+  return N * (N + M) / 2;
+}
+
+}  // namespace
+
+ht_status ht_fail(ht_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -26,69 +36,7 @@ ht_status fail(ht_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HT_HIP(call)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess) return fail(HT_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-size_t elem_bytes(int dtype) { return dtype == HT_C128 ? 16 : 8; }
-
-uint64_t stored_elems(int n, int m) {
-  const uint64_t N = 1ull << n, M = 1ull << m;
-  return N * (N + M) / 2;
-}
-
-struct PendingEvent {
-  int cls;
-  hipEvent_t a, b;
-  double bytes;
-};
-
-}  // namespace
-
-struct ht_herm {
-  int n = 0, m_req = 0, m = 0;
-  int dtype = 0;
-  uint64_t nelems = 0;
-  size_t bytes = 0;
-  void* buf = nullptr;
-  bool owned = false;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int num_cu = 256;
-  // device scratch
-  double* coef_dev = nullptr;   // 512 doubles: two-qubit transfer matrices
-  double* out_dev = nullptr;    // 8 doubles: reduction results
-  double* out_host = nullptr;   // pinned: 8 doubles
-  double* red = nullptr;        // reduction partial sums
-  size_t red_cap = 0;           // doubles
-  void* tmp = nullptr;          // term tables and other per-call uploads
-  size_t tmp_cap = 0;           // bytes
-  // profiling
-  bool prof = false;
-  std::vector<PendingEvent> pending;
-  std::vector<hipEvent_t> pool;
-  int64_t prof_launches[2 * ht::kClassesPerDtype] = {};
-  double prof_ms[2 * ht::kClassesPerDtype] = {};
-  double prof_bytes[2 * ht::kClassesPerDtype] = {};
-};
-
 namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    int cur = 0;
-    if (hipGetDevice(&cur) == hipSuccess && cur != dev) {
-      prev = cur;
-      (void)hipSetDevice(dev);
-    }
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 ht_status ensure_red(ht_herm* h, size_t doubles) {
   if (h->red_cap >= doubles) return HT_OK;
@@ -100,7 +48,7 @@ ht_status ensure_red(ht_herm* h, size_t doubles) {
   }
   if (hipMalloc(&h->red, doubles * sizeof(double)) != hipSuccess) {
     h->red = nullptr;
-    return fail(HT_ENOMEM, "could not allocate %zu bytes of reduction scratch", doubles * 8);
+    return ht_fail(HT_ENOMEM, "could not allocate %zu bytes of reduction scratch", doubles * 8);
   }
   h->red_cap = doubles;
   return HT_OK;
@@ -116,7 +64,7 @@ ht_status ensure_tmp(ht_herm* h, size_t bytes) {
   }
   if (hipMalloc(&h->tmp, bytes) != hipSuccess) {
     h->tmp = nullptr;
-    return fail(HT_ENOMEM, "could not allocate %zu bytes of scratch", bytes);
+    return ht_fail(HT_ENOMEM, "could not allocate %zu bytes of scratch", bytes);
   }
   h->tmp_cap = bytes;
   return HT_OK;
@@ -150,7 +98,7 @@ ht_status build_pauli(int n, int nterms, const uint8_t* codes, const double* coe
     int ny = 0;
     for (int q = 0; q < n; ++q) {
       const uint8_t c = codes[(size_t)t * n + q];
-      if (c > 3) return fail(HT_EINVAL, "Pauli code %d at term %d qubit %d is not in 0..3", c, t, q);
+      if (c > 3) return ht_fail(HT_EINVAL, "Pauli code %d at term %d qubit %d is not in 0..3", c, t, q);
       if (c == 1 || c == 2) x |= 1u << q;
       if (c == 2 || c == 3) z |= 1u << q;
       if (c == 2) ++ny;
@@ -190,19 +138,19 @@ size_t ht_storage_bytes(int n, int tile_log2, ht_dtype dtype) {
 
 ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, size_t buf_bytes,
                          void* hip_stream, ht_herm** out) {
-  if (!out) return fail(HT_EINVAL, "out is NULL");
+  if (!out) return ht_fail(HT_EINVAL, "out is NULL");
   *out = nullptr;
-  if (n < 1 || n > HT_MAX_QUBITS) return fail(HT_EINVAL, "n = %d outside [1, %d]", n, HT_MAX_QUBITS);
+  if (n < 1 || n > HT_MAX_QUBITS) return ht_fail(HT_EINVAL, "n = %d outside [1, %d]", n, HT_MAX_QUBITS);
   if (tile_log2 < HT_MIN_TILE_LOG2 || tile_log2 > HT_MAX_TILE_LOG2)
-    return fail(HT_EINVAL, "tile_log2 = %d outside [%d, %d]", tile_log2, HT_MIN_TILE_LOG2,
+    return ht_fail(HT_EINVAL, "tile_log2 = %d outside [%d, %d]", tile_log2, HT_MIN_TILE_LOG2,
                 HT_MAX_TILE_LOG2);
-  if (dtype != HT_C128 && dtype != HT_C64) return fail(HT_EINVAL, "unknown dtype %d", (int)dtype);
+  if (dtype != HT_C128 && dtype != HT_C64) return ht_fail(HT_EINVAL, "unknown dtype %d", (int)dtype);
   const size_t need = ht_storage_bytes(n, tile_log2, dtype);
   if (dev_buf) {
     if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
-      return fail(HT_EINVAL, "borrowed buffer is not 256-byte aligned");
+      return ht_fail(HT_EINVAL, "borrowed buffer is not 256-byte aligned");
     if (buf_bytes < need)
-      return fail(HT_ENOMEM, "borrowed buffer holds %zu bytes, %zu needed", buf_bytes, need);
+      return ht_fail(HT_ENOMEM, "borrowed buffer holds %zu bytes, %zu needed", buf_bytes, need);
   }
   ht_herm* h = new ht_herm();
   h->n = n;
@@ -216,7 +164,7 @@ ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, si
     ht_herm_destroy(h);
     return st;
   };
-  if (hipGetDevice(&h->device) != hipSuccess) return cleanup(fail(HT_EDEVICE, "no HIP device"));
+  if (hipGetDevice(&h->device) != hipSuccess) return cleanup(ht_fail(HT_EDEVICE, "no HIP device"));
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
       cus > 0)
@@ -227,21 +175,21 @@ ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, si
   } else {
     if (hipMalloc(&h->buf, need) != hipSuccess) {
       h->buf = nullptr;
-      return cleanup(fail(HT_ENOMEM, "could not allocate %zu bytes of tiled storage", need));
+      return cleanup(ht_fail(HT_ENOMEM, "could not allocate %zu bytes of tiled storage", need));
     }
     h->owned = true;
   }
   if (hipMalloc(&h->coef_dev, 512 * sizeof(double)) != hipSuccess) {
     h->coef_dev = nullptr;
-    return cleanup(fail(HT_ENOMEM, "could not allocate coefficient buffer"));
+    return cleanup(ht_fail(HT_ENOMEM, "could not allocate coefficient buffer"));
   }
   if (hipMalloc(&h->out_dev, 8 * sizeof(double)) != hipSuccess) {
     h->out_dev = nullptr;
-    return cleanup(fail(HT_ENOMEM, "could not allocate result buffer"));
+    return cleanup(ht_fail(HT_ENOMEM, "could not allocate result buffer"));
   }
   if (hipHostMalloc(&h->out_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     h->out_host = nullptr;
-    return cleanup(fail(HT_ENOMEM, "could not allocate pinned result buffer"));
+    return cleanup(ht_fail(HT_ENOMEM, "could not allocate pinned result buffer"));
   }
   *out = h;
   return HT_OK;
@@ -249,7 +197,7 @@ ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, si
 
 ht_status ht_herm_destroy(ht_herm* h) {
   if (!h) return HT_OK;
-  DeviceGuard dg(h->device);
+  ht_device_guard dg(h->device);
   (void)hipStreamSynchronize(h->stream);
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
@@ -267,8 +215,8 @@ ht_status ht_herm_destroy(ht_herm* h) {
 }
 
 ht_status ht_herm_set_stream(ht_herm* h, void* hip_stream) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(hipStreamSynchronize(h->stream));
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   return HT_OK;
@@ -276,7 +224,7 @@ ht_status ht_herm_set_stream(ht_herm* h, void* hip_stream) {
 
 ht_status ht_herm_info(const ht_herm* h, int* n, int* tile_log2, int* dtype, void** dev_ptr,
                        size_t* bytes) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
   if (n) *n = h->n;
   if (tile_log2) *tile_log2 = h->m;
   if (dtype) *dtype = h->dtype;
@@ -286,33 +234,33 @@ ht_status ht_herm_info(const ht_herm* h, int* n, int* tile_log2, int* dtype, voi
 }
 
 ht_status ht_herm_synchronize(ht_herm* h) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(hipStreamSynchronize(h->stream));
   return HT_OK;
 }
 
 ht_status ht_herm_init_zero(ht_herm* h) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(ht::launch_fill_zero(h->buf, h->bytes, h->stream));
   return HT_OK;
 }
 
 ht_status ht_herm_init_identity(ht_herm* h, double scale) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(ht::launch_fill_zero(h->buf, h->bytes, h->stream));
   HT_HIP(ht::launch_set_diag(h->dtype, h->buf, h->n, h->m, scale, h->stream));
   return HT_OK;
 }
 
 ht_status ht_herm_init_dense(ht_herm* h, const double* A, int64_t ld, int on_device) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!A) return fail(HT_EINVAL, "A is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!A) return ht_fail(HT_EINVAL, "A is NULL");
   const int64_t N = 1ll << h->n;
-  if (ld < N) return fail(HT_EINVAL, "ld = %lld < N = %lld", (long long)ld, (long long)N);
-  DeviceGuard dg(h->device);
+  if (ld < N) return ht_fail(HT_EINVAL, "ld = %lld < N = %lld", (long long)ld, (long long)N);
+  ht_device_guard dg(h->device);
   if (on_device) {
     HT_HIP(ht::launch_pack_dense(h->dtype, h->buf, h->n, h->m, A, ld, h->stream));
     return HT_OK;
@@ -320,20 +268,20 @@ ht_status ht_herm_init_dense(ht_herm* h, const double* A, int64_t ld, int on_dev
   double* tmp = nullptr;
   const size_t bytes = (size_t)N * (size_t)ld * 16;
   if (hipMalloc(&tmp, bytes) != hipSuccess)
-    return fail(HT_ENOMEM, "could not allocate %zu bytes for the dense upload", bytes);
+    return ht_fail(HT_ENOMEM, "could not allocate %zu bytes for the dense upload", bytes);
   hipError_t e = hipMemcpyAsync(tmp, A, bytes, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = ht::launch_pack_dense(h->dtype, h->buf, h->n, h->m, tmp, ld, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(HT_EDEVICE, "init_dense: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return ht_fail(HT_EDEVICE, "init_dense: %s", hipGetErrorString(e));
   return HT_OK;
 }
 
 ht_status ht_herm_init_lowrank(ht_herm* h, const double* G, int rank, int on_device) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!G) return fail(HT_EINVAL, "G is NULL");
-  if (rank < 1 || rank > 4096) return fail(HT_EINVAL, "rank = %d outside [1, 4096]", rank);
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!G) return ht_fail(HT_EINVAL, "G is NULL");
+  if (rank < 1 || rank > 4096) return ht_fail(HT_EINVAL, "rank = %d outside [1, 4096]", rank);
+  ht_device_guard dg(h->device);
   if (on_device) {
     HT_HIP(ht::launch_lowrank(h->dtype, h->buf, h->n, h->m, G, rank, h->stream));
     return HT_OK;
@@ -341,26 +289,26 @@ ht_status ht_herm_init_lowrank(ht_herm* h, const double* G, int rank, int on_dev
   const size_t bytes = ((size_t)1 << h->n) * (size_t)rank * 16;
   double* tmp = nullptr;
   if (hipMalloc(&tmp, bytes) != hipSuccess)
-    return fail(HT_ENOMEM, "could not allocate %zu bytes for the factor upload", bytes);
+    return ht_fail(HT_ENOMEM, "could not allocate %zu bytes for the factor upload", bytes);
   hipError_t e = hipMemcpyAsync(tmp, G, bytes, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = ht::launch_lowrank(h->dtype, h->buf, h->n, h->m, tmp, rank, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(HT_EDEVICE, "init_lowrank: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return ht_fail(HT_EDEVICE, "init_lowrank: %s", hipGetErrorString(e));
   return HT_OK;
 }
 
 ht_status ht_herm_init_pauli_sum(ht_herm* h, int nterms, const uint8_t* codes,
                                  const double* coeffs) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!codes || !coeffs) return fail(HT_EINVAL, "codes or coeffs is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!codes || !coeffs) return ht_fail(HT_EINVAL, "codes or coeffs is NULL");
   if (nterms < 1 || nterms > kMaxPauliTerms)
-    return fail(HT_EINVAL, "nterms = %d outside [1, %d]", nterms, kMaxPauliTerms);
+    return ht_fail(HT_EINVAL, "nterms = %d outside [1, %d]", nterms, kMaxPauliTerms);
   std::vector<ht::PauliTerm> terms;
   std::vector<ht::PauliGroup> groups;
   ht_status st = build_pauli(h->n, nterms, codes, coeffs, terms, groups);
   if (st != HT_OK) return st;
-  DeviceGuard dg(h->device);
+  ht_device_guard dg(h->device);
   const size_t tb = terms.size() * sizeof(ht::PauliTerm), gb = groups.size() * sizeof(ht::PauliGroup);
   st = ensure_tmp(h, tb + gb);
   if (st != HT_OK) return st;
@@ -378,11 +326,11 @@ ht_status ht_herm_init_pauli_sum(ht_herm* h, int nterms, const uint8_t* codes,
 
 ht_status ht_herm_to_dense(const ht_herm* hc, double* out, int64_t ld, int on_device) {
   ht_herm* h = const_cast<ht_herm*>(hc);
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!out) return fail(HT_EINVAL, "out is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!out) return ht_fail(HT_EINVAL, "out is NULL");
   const int64_t N = 1ll << h->n;
-  if (ld < N) return fail(HT_EINVAL, "ld = %lld < N = %lld", (long long)ld, (long long)N);
-  DeviceGuard dg(h->device);
+  if (ld < N) return ht_fail(HT_EINVAL, "ld = %lld < N = %lld", (long long)ld, (long long)N);
+  ht_device_guard dg(h->device);
   if (on_device) {
     HT_HIP(ht::launch_unpack_dense(h->dtype, h->buf, h->n, h->m, out, ld, h->stream));
     return HT_OK;
@@ -390,28 +338,28 @@ ht_status ht_herm_to_dense(const ht_herm* hc, double* out, int64_t ld, int on_de
   const size_t bytes = (size_t)N * (size_t)ld * 16;
   double* tmp = nullptr;
   if (hipMalloc(&tmp, bytes) != hipSuccess)
-    return fail(HT_ENOMEM, "could not allocate %zu bytes for the dense download", bytes);
+    return ht_fail(HT_ENOMEM, "could not allocate %zu bytes for the dense download", bytes);
   hipError_t e = ht::launch_fill_zero(tmp, bytes, h->stream);
   if (e == hipSuccess) e = ht::launch_unpack_dense(h->dtype, h->buf, h->n, h->m, tmp, ld, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(HT_EDEVICE, "to_dense: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return ht_fail(HT_EDEVICE, "to_dense: %s", hipGetErrorString(e));
   return HT_OK;
 }
 
 ht_status ht_herm_get_entries(const ht_herm* hc, int64_t count, const int64_t* rows,
                               const int64_t* cols, double* out) {
   ht_herm* h = const_cast<ht_herm*>(hc);
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!rows || !cols || !out) return fail(HT_EINVAL, "rows, cols or out is NULL");
-  if (count < 1 || count > (1ll << 24)) return fail(HT_EINVAL, "count outside [1, 2^24]");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!rows || !cols || !out) return ht_fail(HT_EINVAL, "rows, cols or out is NULL");
+  if (count < 1 || count > (1ll << 24)) return ht_fail(HT_EINVAL, "count outside [1, 2^24]");
   const int64_t N = 1ll << h->n;
   for (int64_t e = 0; e < count; ++e)
     if (rows[e] < 0 || rows[e] >= N || cols[e] < 0 || cols[e] >= N)
-      return fail(HT_EINVAL, "entry %lld: (%lld, %lld) outside the matrix", (long long)e,
+      return ht_fail(HT_EINVAL, "entry %lld: (%lld, %lld) outside the matrix", (long long)e,
                   (long long)rows[e], (long long)cols[e]);
-  DeviceGuard dg(h->device);
+  ht_device_guard dg(h->device);
   const size_t ib = (size_t)count * 8, ob = (size_t)count * 16;
   ht_status st = ensure_tmp(h, 2 * ib + ob);
   if (st != HT_OK) return st;
@@ -430,23 +378,23 @@ ht_status ht_herm_get_entries(const ht_herm* hc, int64_t count, const int64_t* r
 
 ht_status ht_herm_read_raw(const ht_herm* hc, size_t offset, size_t nbytes, void* out) {
   ht_herm* h = const_cast<ht_herm*>(hc);
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!out) return fail(HT_EINVAL, "out is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!out) return ht_fail(HT_EINVAL, "out is NULL");
   if (offset > h->bytes || nbytes > h->bytes - offset)
-    return fail(HT_EINVAL, "range [%zu, %zu) outside the %zu-byte storage", offset, offset + nbytes,
+    return ht_fail(HT_EINVAL, "range [%zu, %zu) outside the %zu-byte storage", offset, offset + nbytes,
                 h->bytes);
-  DeviceGuard dg(h->device);
+  ht_device_guard dg(h->device);
   HT_HIP(hipStreamSynchronize(h->stream));
   HT_HIP(hipMemcpy(out, reinterpret_cast<char*>(h->buf) + offset, nbytes, hipMemcpyDeviceToHost));
   return HT_OK;
 }
 
 ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src) {
-  if (!dst || !src) return fail(HT_EINVAL, "handle is NULL");
+  if (!dst || !src) return ht_fail(HT_EINVAL, "handle is NULL");
   if (dst->n != src->n || dst->m != src->m || dst->dtype != src->dtype)
-    return fail(HT_EINVAL, "copy needs equal n, tile edge and dtype");
+    return ht_fail(HT_EINVAL, "copy needs equal n, tile edge and dtype");
   if (dst == src) return HT_OK;
-  DeviceGuard dg(dst->device);
+  ht_device_guard dg(dst->device);
   if (src->stream != dst->stream) HT_HIP(hipStreamSynchronize(src->stream));
   HT_HIP(ht::launch_copy(dst->buf, src->buf, dst->bytes, dst->stream));
   return HT_OK;
@@ -454,28 +402,28 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src) {
 
 static ht_status apply(ht_herm* h, int k, const int* targets, int r, const double* mats,
                        ht_picture picture) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
   if (picture != HT_SCHRODINGER && picture != HT_HEISENBERG)
-    return fail(HT_EINVAL, "unknown picture %d", (int)picture);
+    return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   ht::PreparedOp op;
   char msg[256];
   if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
                      sizeof msg) != 0)
-    return fail(HT_EINVAL, "%s", msg);
-  DeviceGuard dg(h->device);
+    return ht_fail(HT_EINVAL, "%s", msg);
+  ht_device_guard dg(h->device);
   if (op.k == 2 && op.form == 1) HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 512, h->stream));
   hipEvent_t a = nullptr, b = nullptr;
   if (h->prof) {
     a = take_event(h);
     b = take_event(h);
-    if (!a || !b) return fail(HT_EDEVICE, "could not create profiling events");
+    if (!a || !b) return ht_fail(HT_EDEVICE, "could not create profiling events");
     HT_HIP(hipEventRecord(a, h->stream));
   }
   HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
   if (h->prof) {
     HT_HIP(hipEventRecord(b, h->stream));
     const int cls = h->dtype * ht::kClassesPerDtype + ht::conj_class(op.k, op.ncross, op.form);
-    h->pending.push_back(PendingEvent{cls, a, b, 2.0 * (double)h->bytes});
+    h->pending.push_back(ht_pending_event{cls, a, b, 2.0 * (double)h->bytes});
   }
   return HT_OK;
 }
@@ -492,9 +440,9 @@ ht_status ht_apply_channel(ht_herm* h, int k, const int* targets, int r, const d
 
 ht_status ht_trace(const ht_herm* hc, double* out) {
   ht_herm* h = const_cast<ht_herm*>(hc);
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!out) return fail(HT_EINVAL, "out is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!out) return ht_fail(HT_EINVAL, "out is NULL");
+  ht_device_guard dg(h->device);
   ht_status st = ensure_red(h, ht::reduce_scratch_doubles(h->n, h->m, 0));
   if (st != HT_OK) return st;
   HT_HIP(ht::launch_trace(h->dtype, h->buf, h->n, h->m, h->red, h->out_dev, h->stream));
@@ -503,11 +451,11 @@ ht_status ht_trace(const ht_herm* hc, double* out) {
 
 ht_status ht_expectation(const ht_herm* a, const ht_herm* b, double* out) {
   ht_herm* h = const_cast<ht_herm*>(a);
-  if (!a || !b) return fail(HT_EINVAL, "handle is NULL");
-  if (!out) return fail(HT_EINVAL, "out is NULL");
+  if (!a || !b) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!out) return ht_fail(HT_EINVAL, "out is NULL");
   if (a->n != b->n || a->m != b->m || a->dtype != b->dtype)
-    return fail(HT_EINVAL, "expectation needs equal n, tile edge and dtype");
-  DeviceGuard dg(h->device);
+    return ht_fail(HT_EINVAL, "expectation needs equal n, tile edge and dtype");
+  ht_device_guard dg(h->device);
   if (b->stream != a->stream) HT_HIP(hipStreamSynchronize(b->stream));
   ht_status st = ensure_red(h, ht::reduce_scratch_doubles(h->n, h->m, 0));
   if (st != HT_OK) return st;
@@ -519,15 +467,15 @@ ht_status ht_expectation(const ht_herm* a, const ht_herm* b, double* out) {
 ht_status ht_expectation_pauli_sum(const ht_herm* hc, int nterms, const uint8_t* codes,
                                    const double* coeffs, double* out) {
   ht_herm* h = const_cast<ht_herm*>(hc);
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  if (!codes || !coeffs || !out) return fail(HT_EINVAL, "codes, coeffs or out is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  if (!codes || !coeffs || !out) return ht_fail(HT_EINVAL, "codes, coeffs or out is NULL");
   if (nterms < 1 || nterms > kMaxPauliTerms)
-    return fail(HT_EINVAL, "nterms = %d outside [1, %d]", nterms, kMaxPauliTerms);
+    return ht_fail(HT_EINVAL, "nterms = %d outside [1, %d]", nterms, kMaxPauliTerms);
   std::vector<ht::PauliTerm> terms;
   std::vector<ht::PauliGroup> groups;
   ht_status st = build_pauli(h->n, nterms, codes, coeffs, terms, groups);
   if (st != HT_OK) return st;
-  DeviceGuard dg(h->device);
+  ht_device_guard dg(h->device);
   st = ensure_red(h, ht::reduce_scratch_doubles(h->n, h->m, nterms));
   if (st != HT_OK) return st;
   const size_t tb = terms.size() * sizeof(ht::PauliTerm);
@@ -542,21 +490,21 @@ ht_status ht_expectation_pauli_sum(const ht_herm* hc, int nterms, const uint8_t*
 }
 
 ht_status ht_scale(ht_herm* h, double alpha) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(ht::launch_scale(h->dtype, h->buf, h->nelems, alpha, h->stream));
   return HT_OK;
 }
 
 ht_status ht_profile_enable(ht_herm* h, int enable) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
   h->prof = enable != 0;
   return HT_OK;
 }
 
 ht_status ht_profile_reset(ht_herm* h) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(hipStreamSynchronize(h->stream));
   for (auto& p : h->pending) {
     h->pool.push_back(p.a);
@@ -571,8 +519,8 @@ ht_status ht_profile_reset(ht_herm* h) {
 
 ht_status ht_profile_read(ht_herm* h, int max_classes, int* nclasses, int64_t* launches,
                           double* ms, double* bytes) {
-  if (!h) return fail(HT_EINVAL, "handle is NULL");
-  DeviceGuard dg(h->device);
+  if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
+  ht_device_guard dg(h->device);
   HT_HIP(hipStreamSynchronize(h->stream));
   for (auto& p : h->pending) {
     float t = 0.f;
@@ -606,43 +554,43 @@ const char* ht_kernel_class_name(int idx) {
 }
 
 ht_status ht_set_tuning(const char* name, int64_t value) {
-  if (!name) return fail(HT_EINVAL, "name is NULL");
+  if (!name) return ht_fail(HT_EINVAL, "name is NULL");
   const std::string k(name);
   if (k == "conj_wg_per_cu") {
-    if (value < 1 || value > 64) return fail(HT_EINVAL, "conj_wg_per_cu must be in [1, 64]");
+    if (value < 1 || value > 64) return ht_fail(HT_EINVAL, "conj_wg_per_cu must be in [1, 64]");
     ht::tuning().wg_per_cu = (int)value;
     return HT_OK;
   }
   if (k == "conj_block_threads") {
     if (value != 64 && value != 128 && value != 256)
-      return fail(HT_EINVAL, "conj_block_threads must be 64, 128 or 256");
+      return ht_fail(HT_EINVAL, "conj_block_threads must be 64, 128 or 256");
     ht::tuning().block_threads = (int)value;
     return HT_OK;
   }
   if (k == "conj_order") {
-    if (value < 0 || value > 1) return fail(HT_EINVAL, "conj_order must be 0 or 1");
+    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "conj_order must be 0 or 1");
     ht::tuning().order = (int)value;
     return HT_OK;
   }
   if (k == "conj_mem_mode") {
-    if (value < 0 || value > 3) return fail(HT_EINVAL, "conj_mem_mode must be in [0, 3]");
+    if (value < 0 || value > 3) return ht_fail(HT_EINVAL, "conj_mem_mode must be in [0, 3]");
     ht::tuning().mem_mode = (int)value;
     return HT_OK;
   }
-  return fail(HT_EINVAL, "unknown tuning parameter '%s'", name);
+  return ht_fail(HT_EINVAL, "unknown tuning parameter '%s'", name);
 }
 
 ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
                         const double* kraus, ht_picture picture, int* sorted_targets, int* ncross,
                         int* form, double* coef) {
   const int m = ht_effective_tile_log2(n, tile_log2);
-  if (m < 0) return fail(HT_EINVAL, "n or tile_log2 out of range");
+  if (m < 0) return ht_fail(HT_EINVAL, "n or tile_log2 out of range");
   if (picture != HT_SCHRODINGER && picture != HT_HEISENBERG)
-    return fail(HT_EINVAL, "unknown picture %d", (int)picture);
+    return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   ht::PreparedOp op;
   char msg[256];
   if (ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg, sizeof msg) != 0)
-    return fail(HT_EINVAL, "%s", msg);
+    return ht_fail(HT_EINVAL, "%s", msg);
   if (sorted_targets)
     for (int l = 0; l < op.k; ++l) sorted_targets[l] = op.sorted[l];
   if (ncross) *ncross = op.ncross;

@@ -406,7 +406,7 @@ HT_HD void conj_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const GroupC
 // Geometry of a pass for an n-qubit operator with effective tile exponent m
 // and ascending targets sorted[0..K) of which the last C are cross targets.
 template <int K, int C>
-inline ConjGeom<K, C> make_geom(int n, int m, const int* sorted) {
+HT_HD ConjGeom<K, C> make_geom(int n, int m, const int* sorted) {
   ConjGeom<K, C> g{};
   constexpr int KI = K - C;
   g.m = m;

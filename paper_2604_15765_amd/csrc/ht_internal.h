@@ -68,6 +68,28 @@ hipError_t launch_expectation(int dtype, const void* a, const void* b, int n, in
 hipError_t launch_pauli_expect(int dtype, const void* buf, int n, int m, const PauliTerm* terms,
                                int nterms, double* scratch, double* out_dev, hipStream_t s);
 
+// One op of a batch in device form (see ht_batch.hip).
+struct BatchOp {
+  int32_t k, ncross, form;
+  int32_t sorted[2];
+  uint32_t coef_off;  // offset (in doubles) of its coefficients in the batch's array
+};
+// One operator of a batch: its storage, shape and op range.
+struct BatchOperator {
+  void* buf;
+  uint64_t bytes;
+  int32_t n, m;
+  uint32_t op_begin, op_end;
+  int32_t in_lds, pad;
+};
+// Enqueue a queue reset and one persistent batch launch (grid workgroups of
+// threads threads; lds_bytes of dynamic LDS for operators staged in LDS).
+hipError_t launch_batch(int dtype, const BatchOperator* opers, unsigned nopers, const BatchOp* ops,
+                        const double* coefs, unsigned* counter, int threads, int grid,
+                        size_t lds_bytes, hipStream_t s);
+// Allow the batch kernel to use up to bytes of dynamic LDS.
+hipError_t set_batch_lds_limit(int dtype, size_t bytes);
+
 // Upload up to 512 doubles into a device buffer with stream-ordered kernels
 // (the values travel as kernel arguments, so no host buffer must outlive the
 // call and no pageable-memory copy is involved).

@@ -1,0 +1,128 @@
+"""Batched persistent launches and captured graphs, against one-call-at-a-time
+application and the CPU oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ht():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_15765_amd as ht
+    return ht
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _random_circuit(n, nops, rng):
+    ops = []
+    for _ in range(nops):
+        c = rng.random()
+        if c < 0.4 or n < 2:
+            ops.append(synth.random_ops.unitary_op([int(rng.integers(n))], synth.haar_unitary(2, rng)))
+        elif c < 0.7:
+            t = [int(x) for x in rng.choice(n, 2, replace=False)]
+            ops.append(synth.random_ops.unitary_op(t, synth.haar_unitary(4, rng)))
+        elif c < 0.9:
+            ops.append(synth.random_ops.channel_op([int(rng.integers(n))], synth.random_kraus_set(1, 3, rng)))
+        else:
+            t = [int(x) for x in rng.choice(n, 2, replace=False)]
+            ops.append(synth.random_ops.channel_op(t, synth.random_kraus_set(2, 3, rng)))
+    return ops
+
+
+def _cases(rng, count):
+    out = []
+    for i in range(count):
+        n = int(rng.integers(1, 10))
+        m = int(rng.choice([2, 3, 5]))
+        dtype = "c64" if i % 5 == 4 else "c128"
+        out.append((n, m, dtype, synth.random_hermitian_dense(n, rng), _random_circuit(n, int(rng.integers(5, 30)), rng)))
+    return out
+
+
+@pytest.mark.parametrize("params", [dict(), dict(lds_max_bytes=0), dict(threads=1024, wg_per_cu=1),
+                                    dict(threads=64, wg_per_cu=8)])
+def test_batch_equals_plain_bitwise(ht, params):
+    """One persistent launch over 40 operators of mixed n, tile edge and
+    storage type gives bitwise the same storage as applying every op with its
+    own launch, and matches the oracle."""
+    rng = synth.make_rng(1000)
+    cases = _cases(rng, 40)
+    batch = ht.Batch(**params)
+    pairs = []
+    for n, m, dtype, H, ops in cases:
+        a = ht.Herm(n, m, dtype).init_dense(H)
+        b = ht.Herm(n, m, dtype).init_dense(H)
+        for op in ops:
+            batch.add_op(a, op)
+            b.apply_op(op)
+        pairs.append((a, b, H, ops, dtype))
+    assert batch.size() == (len(cases), sum(len(c[4]) for c in cases))
+    batch.run()
+    torch.cuda.synchronize()
+    for a, b, H, ops, dtype in pairs:
+        assert np.array_equal(a.read_raw(), b.read_raw()), (a.n, a.tile_log2, dtype)
+        ref = oracle.apply_ops(H if dtype == "c128" else H.astype(np.complex64).astype(np.complex128), ops)
+        tol = 1e-12 if dtype == "c128" else (len(ops) + 1) * 2.0 ** -24 * 4
+        assert rel(a.to_dense(), ref) <= tol, (a.n, dtype, rel(a.to_dense(), ref))
+    batch.close()
+
+
+def test_batch_heisenberg_and_reuse(ht):
+    """Heisenberg-picture ops in a batch; a batch can be cleared and refilled."""
+    rng = synth.make_rng(1001)
+    batch = ht.Batch()
+    for round_ in range(2):
+        hs = []
+        for n in (3, 6, 8):
+            H = synth.random_hermitian_dense(n, rng)
+            ops = _random_circuit(n, 12, rng)
+            h = ht.Herm(n, 3).init_dense(H)
+            for op in reversed(ops):
+                batch.add_op(h, op, ht.HEISENBERG)
+            hs.append((h, H, ops))
+        batch.run()
+        torch.cuda.synchronize()
+        for h, H, ops in hs:
+            ref = oracle.apply_ops(H, list(reversed(ops)), adjoint=True)
+            assert rel(h.to_dense(), ref) <= 1e-12
+        batch.clear()
+        assert batch.size() == (0, 0)
+
+
+def test_graph_replays_match_eager(ht):
+    """A captured op sequence replayed three times, with eager work and
+    synchronisation between replays: every replay equals eager application."""
+    rng = synth.make_rng(1002)
+    n, m = 7, 3
+    H = synth.random_hermitian_dense(n, rng)
+    ops = _random_circuit(n, 25, rng)
+    s = torch.cuda.Stream()
+    h = ht.Herm(n, m, stream=s).init_dense(H)
+    ref = ht.Herm(n, m).init_dense(H)
+    for op in ops:
+        ref.apply_op(op)
+    expect = ref.read_raw()
+    torch.cuda.synchronize()
+    ht.capture_begin(s)
+    for op in ops:
+        h.apply_op(op)
+    g = ht.capture_end(s)
+    for rep in range(3):
+        h.init_dense(H)
+        tr = h.trace()  # eager work between replays
+        assert abs(tr - oracle.trace(H)) < 1e-12
+        g.launch(s)
+        s.synchronize()
+        assert np.array_equal(h.read_raw(), expect), rep
+    g.close()
