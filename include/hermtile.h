@@ -257,6 +257,78 @@ ht_status ht_capture_end(void* hip_stream, ht_graph** out);
 ht_status ht_graph_launch(ht_graph* g, void* hip_stream);
 ht_status ht_graph_destroy(ht_graph* g);
 
+/* --------------------------------------------------------------- server -- */
+
+/* A request server with continuous batching.  A scheduler thread admits
+ * requests first-come first-served when a slot and enough of the HBM budget
+ * are free, keeps each operator resident until its readout, advances small
+ * operators (n <= batch_max_qubits) in rounds of one batched launch each
+ * (requests join and leave between rounds) and large ones on their own
+ * streams in chunks of plain passes, so the work of different requests
+ * overlaps on the device.  A request's result does not depend on what else
+ * is being served.  fifo = 1 serves one request at a time with plain
+ * launches (the baseline).  One device (current at creation). */
+typedef struct ht_server ht_server;
+
+typedef struct {
+  size_t budget_bytes;   /* HBM for resident operators (and their inputs) */
+  int max_active;        /* requests resident at once, 1..256 */
+  int batch_max_qubits;  /* n <= this: batched path; larger: plain passes */
+  int chunk_ops;         /* ops per small request per batched round */
+  int large_chunk_ops;   /* ops per chunk of a large request */
+  int tile_log2;         /* tile edge exponent of every operator */
+  int fifo;              /* 1: one request at a time, plain launches */
+  int batch_threads;     /* see ht_batch_set_param */
+  int batch_wg_per_cu;
+  size_t lds_max_bytes;
+} ht_server_config;
+
+/* Defaults: 200 GiB budget, 32 active, batched up to n = 11, 64 ops per
+ * round, 4 ops per large chunk, tile edge 32, continuous batching. */
+void ht_server_config_default(ht_server_config* cfg);
+
+/* A request: initial state G G^dagger / tr(G G^dagger) for the host N x rank
+ * complex matrix G (row-major, 1 <= rank <= 4096); nops ops, op i acting on
+ * op_k[i] in {1, 2} qubits op_targets[2i..2i+op_k[i]) with op_r[i] matrices
+ * (1 = unitary) read consecutively from op_mats (row-major complex, as
+ * ht_apply_channel); picture applies to every op; readout: tr(rho O) for the
+ * Pauli sum (codes/coeffs as ht_herm_init_pauli_sum, nterms <= 4096) or, with
+ * nterms = 0, the trace.  Everything is copied during ht_server_submit. */
+typedef struct {
+  int n;
+  int dtype;
+  int rank;
+  const double* G;
+  int nops;
+  const int* op_k;
+  const int* op_targets;
+  const int* op_r;
+  const double* op_mats;
+  int picture;
+  int nterms;
+  const uint8_t* codes;
+  const double* coeffs;
+} ht_request;
+
+ht_status ht_server_create(const ht_server_config* cfg, ht_server** out);
+/* Validate and queue a request (HT_EINVAL for a malformed request or one
+ * larger than the budget; nothing is queued then).  *id receives its id. */
+ht_status ht_server_submit(ht_server* s, const ht_request* req, int64_t* id);
+/* Block until every submitted request has completed (HT_EDEVICE on timeout). */
+ht_status ht_server_wait_idle(ht_server* s, double timeout_s);
+/* Move up to max completed requests out of the server: id, status (HT_OK or
+ * the failure), readout value and the times (seconds on the server's
+ * monotonic clock) of submission, admission and completion.  Any output
+ * array may be NULL.  *count receives the number written. */
+ht_status ht_server_poll(ht_server* s, int64_t max, int64_t* ids, int* status, double* values,
+                         double* t_submit, double* t_admit, double* t_done, int64_t* count);
+/* Current time on the server's clock. */
+ht_status ht_server_now(const ht_server* s, double* t);
+/* First asynchronous failure seen by the scheduler ("" if none). */
+ht_status ht_server_last_error(ht_server* s, char* buf, size_t len);
+/* Finish every submitted request, stop the scheduler, free everything. */
+ht_status ht_server_destroy(ht_server* s);
+
 /* --------------------------------------------------------- diagnostics -- */
 
 /* Message describing the last error on the calling thread ("" if none). */

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch  # first: the library must bind to the HIP runtime torch has loaded
 
-__all__ = ["Herm", "Batch", "Graph", "capture_begin", "capture_end", "lib", "SCHRODINGER",
+__all__ = ["Herm", "Batch", "Graph", "Server", "capture_begin", "capture_end", "lib", "SCHRODINGER",
            "HEISENBERG", "HermError", "storage_bytes", "effective_tile_log2", "prepare_op",
            "kernel_class_names", "set_tuning"]
 
@@ -100,6 +100,14 @@ def _load():
         "ht_capture_end": (c_int, [vp, P(vp)]),
         "ht_graph_launch": (c_int, [vp, vp]),
         "ht_graph_destroy": (c_int, [vp]),
+        "ht_server_config_default": (None, [vp]),
+        "ht_server_create": (c_int, [vp, P(vp)]),
+        "ht_server_submit": (c_int, [vp, vp, P(c_int64)]),
+        "ht_server_wait_idle": (c_int, [vp, c_double]),
+        "ht_server_poll": (c_int, [vp, c_int64, vp, vp, vp, vp, vp, vp, P(c_int64)]),
+        "ht_server_now": (c_int, [vp, P(c_double)]),
+        "ht_server_last_error": (c_int, [vp, ctypes.c_char_p, c_size_t]),
+        "ht_server_destroy": (c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -446,3 +454,94 @@ def capture_end(stream) -> Graph:
     g = ctypes.c_void_p()
     _check(lib.ht_capture_end(_stream_ptr(stream), ctypes.byref(g)))
     return Graph(g)
+
+
+class ServerConfig(ctypes.Structure):
+    """ht_server_config."""
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int),
+                ("batch_max_qubits", ctypes.c_int), ("chunk_ops", ctypes.c_int),
+                ("large_chunk_ops", ctypes.c_int), ("tile_log2", ctypes.c_int), ("fifo", ctypes.c_int),
+                ("batch_threads", ctypes.c_int), ("batch_wg_per_cu", ctypes.c_int),
+                ("lds_max_bytes", ctypes.c_size_t)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("rank", ctypes.c_int),
+                ("G", ctypes.c_void_p), ("nops", ctypes.c_int), ("op_k", ctypes.c_void_p),
+                ("op_targets", ctypes.c_void_p), ("op_r", ctypes.c_void_p), ("op_mats", ctypes.c_void_p),
+                ("picture", ctypes.c_int), ("nterms", ctypes.c_int), ("codes", ctypes.c_void_p),
+                ("coeffs", ctypes.c_void_p)]
+
+
+class Server:
+    """ht_server: continuous-batching request server on the current device."""
+
+    def __init__(self, **cfg):
+        c = ServerConfig()
+        lib.ht_server_config_default(ctypes.byref(c))
+        for k, v in cfg.items():
+            if not hasattr(c, k):
+                raise ValueError(f"unknown server option {k}")
+            setattr(c, k, int(v))
+        self.config = {f: getattr(c, f) for f, _ in ServerConfig._fields_}
+        s = ctypes.c_void_p()
+        _check(lib.ht_server_create(ctypes.byref(c), ctypes.byref(s)))
+        self._s = s
+
+    def submit(self, n: int, G, ops, pauli=None, dtype: str = "c128", picture: int = SCHRODINGER) -> int:
+        """Queue a request: state G G^dagger / tr, ops (objects with targets and
+        mats), readout tr(rho O) for pauli = (codes, coeffs) or the trace."""
+        G = _c128(G)
+        k = np.array([len(op.targets) for op in ops], dtype=np.int32)
+        tg = np.zeros(2 * len(ops), dtype=np.int32)
+        for i, op in enumerate(ops):
+            tg[2 * i:2 * i + len(op.targets)] = op.targets
+        r = np.array([op.mats.shape[0] for op in ops], dtype=np.int32)
+        mats = (np.ascontiguousarray(np.concatenate([np.asarray(op.mats, np.complex128).reshape(-1) for op in ops]))
+                if ops else np.zeros(1, np.complex128))
+        req = _Request(n=n, dtype=_DTYPES[dtype], rank=G.shape[1], G=G.ctypes.data, nops=len(ops),
+                       op_k=k.ctypes.data, op_targets=tg.ctypes.data, op_r=r.ctypes.data,
+                       op_mats=mats.ctypes.data, picture=picture, nterms=0, codes=None, coeffs=None)
+        if pauli is not None:
+            codes = np.ascontiguousarray(pauli[0], dtype=np.uint8)
+            coeffs = np.ascontiguousarray(pauli[1], dtype=np.float64)
+            req.nterms, req.codes, req.coeffs = codes.shape[0], codes.ctypes.data, coeffs.ctypes.data
+        rid = ctypes.c_int64()
+        _check(lib.ht_server_submit(self._s, ctypes.byref(req), ctypes.byref(rid)))
+        return rid.value
+
+    def wait_idle(self, timeout_s: float = 600.0) -> None:
+        _check(lib.ht_server_wait_idle(self._s, float(timeout_s)))
+
+    def poll(self, max_results: int = 1 << 16):
+        ids = np.zeros(max_results, np.int64)
+        st = np.zeros(max_results, np.int32)
+        vals = np.zeros(max_results, np.float64)
+        ts, ta, td = (np.zeros(max_results, np.float64) for _ in range(3))
+        cnt = ctypes.c_int64()
+        _check(lib.ht_server_poll(self._s, max_results, _ptr(ids), _ptr(st), _ptr(vals), _ptr(ts), _ptr(ta),
+                                  _ptr(td), ctypes.byref(cnt)))
+        c = cnt.value
+        return [dict(id=int(ids[i]), status=int(st[i]), value=float(vals[i]), t_submit=float(ts[i]),
+                     t_admit=float(ta[i]), t_done=float(td[i])) for i in range(c)]
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _check(lib.ht_server_now(self._s, ctypes.byref(t)))
+        return t.value
+
+    def last_error(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(lib.ht_server_last_error(self._s, buf, 512))
+        return buf.value.decode()
+
+    def close(self) -> None:
+        if getattr(self, "_s", None):
+            _check(lib.ht_server_destroy(self._s))
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

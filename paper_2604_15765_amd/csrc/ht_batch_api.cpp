@@ -10,6 +10,7 @@
 #include "hermtile.h"
 #include "ht_handle.h"
 #include "ht_internal.h"
+#include "ht_batch_runner.h"
 #include "ht_prep.h"
 
 struct ht_batch {
@@ -22,18 +23,8 @@ struct ht_batch {
   std::unordered_map<ht_herm*, size_t> index;
   int device = 0;
   int num_cu = 256;
-  int threads = 256;
-  int wg_per_cu = 2;
-  size_t lds_max = 64 * 1024;
-  size_t lds_set[2] = {0, 0};
-  // device tables, per dtype: [opers | ops | coefs], and two queue counters
-  void* dev = nullptr;
-  size_t dev_cap = 0;
-  unsigned* counters = nullptr;
-  void* stage = nullptr;  // pinned host staging of the tables
-  size_t stage_cap = 0;
-  hipEvent_t done = nullptr;
-  bool pending = false;
+  ht::BatchSchedule sched;
+  ht::BatchRunner runner;
 };
 
 struct ht_graph {
@@ -42,8 +33,6 @@ struct ht_graph {
 };
 
 namespace {
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, const double* mats,
                  ht_picture picture) {
@@ -98,14 +87,7 @@ ht_status ht_batch_create(ht_batch** out) {
 ht_status ht_batch_destroy(ht_batch* b) {
   if (!b) return HT_OK;
   ht_device_guard dg(b->device);
-  if (b->done) {
-    (void)hipEventSynchronize(b->done);
-    (void)hipEventDestroy(b->done);
-  }
-  if (b->dev) (void)hipFree(b->dev);
-  if (b->counters) (void)hipFree(b->counters);
-  if (b->stage) (void)hipHostFree(b->stage);
-  delete b;
+  delete b;  // the runner waits for its last launch and frees its tables
   return HT_OK;
 }
 
@@ -115,13 +97,13 @@ ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value) {
   if (k == "threads") {
     if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
       return ht_fail(HT_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
-    b->threads = (int)value;
+    b->sched.threads = (int)value;
   } else if (k == "wg_per_cu") {
     if (value < 1 || value > 32) return ht_fail(HT_EINVAL, "wg_per_cu must be in [1, 32]");
-    b->wg_per_cu = (int)value;
+    b->sched.wg_per_cu = (int)value;
   } else if (k == "lds_max_bytes") {
     if (value < 0 || value > 160 * 1024) return ht_fail(HT_EINVAL, "lds_max_bytes must be in [0, 163840]");
-    b->lds_max = (size_t)value;
+    b->sched.lds_max = (size_t)value;
   } else {
     return ht_fail(HT_EINVAL, "unknown batch parameter '%s'", name);
   }
@@ -159,11 +141,6 @@ ht_status ht_batch_run(ht_batch* b, void* hip_stream) {
   if (b->entries.empty()) return HT_OK;
   ht_device_guard dg(b->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  // the staging buffer may still feed the previous run's copies
-  if (b->pending) {
-    HT_HIP(hipEventSynchronize(b->done));
-    b->pending = false;
-  }
   // earlier work on the operators' own streams must be complete
   std::vector<hipStream_t> seen;
   for (const auto& e : b->entries)
@@ -171,98 +148,13 @@ ht_status ht_batch_run(ht_batch* b, void* hip_stream) {
       seen.push_back(e.h->stream);
       HT_HIP(hipStreamSynchronize(e.h->stream));
     }
-  // order: per dtype, largest work first (longest-processing-time-first queue)
-  std::vector<size_t> order[2];
-  for (size_t i = 0; i < b->entries.size(); ++i) order[b->entries[i].h->dtype].push_back(i);
-  for (auto& o : order)
-    std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) {
-      const auto& a = b->entries[x];
-      const auto& c = b->entries[y];
-      return (double)a.h->bytes * a.ops.size() > (double)c.h->bytes * c.ops.size();
-    });
-  size_t nopers[2] = {order[0].size(), order[1].size()}, nops[2] = {0, 0}, ncoef[2] = {0, 0};
-  for (int d = 0; d < 2; ++d)
-    for (size_t i : order[d]) {
-      nops[d] += b->entries[i].ops.size();
-      ncoef[d] += b->entries[i].coefs.size();
-    }
-  // layout of the tables (identical in the staging buffer and on the device)
-  size_t off_opers[2], off_ops[2], off_coef[2], total = 0;
-  for (int d = 0; d < 2; ++d) {
-    off_opers[d] = total;
-    total = align_up(total + nopers[d] * sizeof(ht::BatchOperator), 256);
-    off_ops[d] = total;
-    total = align_up(total + nops[d] * sizeof(ht::BatchOp), 256);
-    off_coef[d] = total;
-    total = align_up(total + ncoef[d] * sizeof(double), 256);
-  }
-  if (b->stage_cap < total) {
-    if (b->stage) HT_HIP(hipHostFree(b->stage));
-    b->stage = nullptr;
-    b->stage_cap = 0;
-    if (hipHostMalloc(&b->stage, total, hipHostMallocDefault) != hipSuccess)
-      return ht_fail(HT_ENOMEM, "could not allocate %zu bytes of pinned staging", total);
-    b->stage_cap = total;
-  }
-  if (b->dev_cap < total) {
-    if (b->dev) HT_HIP(hipFree(b->dev));
-    b->dev = nullptr;
-    b->dev_cap = 0;
-    if (hipMalloc(&b->dev, total) != hipSuccess)
-      return ht_fail(HT_ENOMEM, "could not allocate %zu bytes of batch tables", total);
-    b->dev_cap = total;
-  }
-  if (!b->counters && hipMalloc(&b->counters, 2 * sizeof(unsigned)) != hipSuccess) {
-    b->counters = nullptr;
-    return ht_fail(HT_ENOMEM, "could not allocate the batch queue counters");
-  }
-  if (!b->done) HT_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
-  char* st = reinterpret_cast<char*>(b->stage);
-  size_t lds_need[2] = {0, 0};
-  for (int d = 0; d < 2; ++d) {
-    auto* opers = reinterpret_cast<ht::BatchOperator*>(st + off_opers[d]);
-    auto* ops = reinterpret_cast<ht::BatchOp*>(st + off_ops[d]);
-    auto* coefs = reinterpret_cast<double*>(st + off_coef[d]);
-    uint32_t op_pos = 0;
-    uint32_t coef_pos = 0;
-    for (size_t r = 0; r < order[d].size(); ++r) {
-      const auto& e = b->entries[order[d][r]];
-      ht::BatchOperator o{};
-      o.buf = e.h->buf;
-      o.bytes = e.h->bytes;
-      o.n = e.h->n;
-      o.m = e.h->m;
-      o.op_begin = op_pos;
-      o.op_end = op_pos + (uint32_t)e.ops.size();
-      o.in_lds = e.h->bytes <= b->lds_max ? 1 : 0;
-      if (o.in_lds) lds_need[d] = std::max(lds_need[d], (size_t)e.h->bytes);
-      opers[r] = o;
-      for (const auto& op : e.ops) {
-        ht::BatchOp x = op;
-        x.coef_off += coef_pos;
-        ops[op_pos++] = x;
-      }
-      std::memcpy(coefs + coef_pos, e.coefs.data(), e.coefs.size() * sizeof(double));
-      coef_pos += (uint32_t)e.coefs.size();
-    }
-  }
-  HT_HIP(hipMemcpyAsync(b->dev, b->stage, total, hipMemcpyHostToDevice, s));
-  char* dv = reinterpret_cast<char*>(b->dev);
-  for (int d = 0; d < 2; ++d) {
-    if (nopers[d] == 0) continue;
-    if (lds_need[d] > b->lds_set[d]) {
-      HT_HIP(ht::set_batch_lds_limit(d, lds_need[d]));
-      b->lds_set[d] = lds_need[d];
-    }
-    int grid = b->num_cu * b->wg_per_cu;
-    if ((size_t)grid > nopers[d]) grid = (int)nopers[d];
-    HT_HIP(ht::launch_batch(d, reinterpret_cast<const ht::BatchOperator*>(dv + off_opers[d]),
-                            (unsigned)nopers[d], reinterpret_cast<const ht::BatchOp*>(dv + off_ops[d]),
-                            reinterpret_cast<const double*>(dv + off_coef[d]), b->counters + d,
-                            b->threads, grid, lds_need[d], s));
-  }
-  HT_HIP(hipEventRecord(b->done, s));
-  b->pending = true;
+  std::vector<ht::BatchItem> items;
+  items.reserve(b->entries.size());
+  for (const auto& e : b->entries)
+    items.push_back(ht::BatchItem{e.h->buf, e.h->bytes, e.h->n, e.h->m, e.h->dtype, e.ops.data(),
+                                  (uint32_t)e.ops.size(), e.coefs.data(),
+                                  (uint32_t)e.coefs.size()});
+  HT_HIP(b->runner.run(items, b->sched, b->num_cu, s));
   return HT_OK;
 }
 

@@ -32,6 +32,9 @@ hipError_t launch_conj(int dtype, void* buf, int n, int m, const PreparedOp& op,
 // Elementwise and reduction kernels over the tiled storage.
 hipError_t launch_fill_zero(void* buf, size_t bytes, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// h /= *denom with denom a device scalar.
+hipError_t launch_scale_inv(int dtype, void* buf, uint64_t nelems, const double* denom,
+                            hipStream_t s);
 hipError_t launch_set_diag(int dtype, void* buf, int n, int m, double value, hipStream_t s);
 hipError_t launch_scale(int dtype, void* buf, uint64_t nelems, double alpha, hipStream_t s);
 hipError_t launch_pack_dense(int dtype, void* buf, int n, int m, const double* A, int64_t ld,

@@ -67,6 +67,20 @@ __global__ void scale_kernel(S2<T>* __restrict__ h, uint64_t nelems, double alph
   }
 }
 
+// h /= *denom (denom read from device memory, e.g. a trace just computed)
+template <typename T>
+__global__ void scale_inv_kernel(S2<T>* __restrict__ h, uint64_t nelems,
+                                 const double* __restrict__ denom) {
+  const double alpha = 1.0 / *denom;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nelems; i += stride) {
+    S2<T> v = h[i];
+    v.x = (T)((double)v.x * alpha);
+    v.y = (T)((double)v.y * alpha);
+    h[i] = v;
+  }
+}
+
 template <typename T>
 __global__ void set_diag_kernel(S2<T>* __restrict__ h, uint64_t N, int m, double value) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -338,6 +352,17 @@ hipError_t launch_scale(int dtype, void* buf, uint64_t nelems, double alpha, hip
                                     reinterpret_cast<S2<double>*>(buf), nelems, alpha),
                  hipLaunchKernelGGL(scale_kernel<float>, dim3(g), dim3(kThreads), 0, s,
                                     reinterpret_cast<S2<float>*>(buf), nelems, alpha));
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_inv(int dtype, void* buf, uint64_t nelems, const double* denom,
+                            hipStream_t s) {
+  const unsigned g = grid_for(nelems, kThreads, 8192);
+  HT_DT_DISPATCH(dtype,
+                 hipLaunchKernelGGL(scale_inv_kernel<double>, dim3(g), dim3(kThreads), 0, s,
+                                    reinterpret_cast<S2<double>*>(buf), nelems, denom),
+                 hipLaunchKernelGGL(scale_inv_kernel<float>, dim3(g), dim3(kThreads), 0, s,
+                                    reinterpret_cast<S2<float>*>(buf), nelems, denom));
   return hipGetLastError();
 }
 
