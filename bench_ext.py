@@ -1,0 +1,300 @@
+"""Benchmarks of the extensions: batched launches, serving, complex64 storage.
+
+    python bench_ext.py batched   [--count 4096]
+    python bench_ext.py serve     [--rates 10,100,1000] [--count 48]
+    python bench_ext.py precision [--layers 4]
+
+Each prints one JSON line.  All inputs are seeded and synthetic (see synth/).
+
+batched:   many independent operators (n ~ U{4..11}, U{20..64} mixed ops
+           each: Haar 1q/2q, depolarising/dephasing) evolved three ways --
+           one launch per op, replayed HIP graphs (one per operator), one
+           persistent batched launch -- with the final states compared
+           bitwise on the device and a stratified sample checked against
+           the CPU oracle.
+serve:     Poisson request streams (n log-uniform in 6..16, 10..300 mixed
+           ops, c128/c64, half with a 64-term Pauli-sum readout) served by the
+           continuous-batching server and by the one-at-a-time baseline on
+           the same requests: circuits/s, p50/p99 latency, equal results.
+precision: the n = 16 layered workload in complex64 storage (FP64
+           arithmetic and reductions) next to complex128: passes/s, and the
+           complex64 error against the complex128 GPU state on sampled
+           entries and against the CPU oracle at n = 11.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ batched
+
+def run_batched(args):
+    import torch
+    import oracle
+    import paper_2604_15765_amd as ht
+    import synth
+
+    torch.cuda.set_device(0)
+    rngs = synth.spawn_rngs(args.seed, args.count)
+    work = []
+    for rng in rngs:
+        n = int(rng.integers(4, 12))
+        G = synth.ginibre_factor(n, min(1 << n, 64), rng)
+        ops = [synth.circuits._random_mixed_op(n, rng, "dephase") for _ in range(int(rng.integers(20, 65)))]
+        work.append((n, G, ops))
+    nops = sum(len(w[2]) for w in work)
+    tile = {n: args.tile_log2 for n in range(1, 12)}
+    log(f"[batched] {args.count} operators, {nops} ops, "
+        f"{sum(ht.storage_bytes(w[0], tile[w[0]]) for w in work) / 1e9:.1f} GB per copy")
+
+    G_dev = [torch.from_numpy(G).to("cuda") for _, G, _ in work]
+
+    def fresh():
+        hs = []
+        for (n, _, _), g in zip(work, G_dev):
+            h = ht.Herm(n, tile[n]).init_lowrank(g)
+            h.scale(1.0 / h.trace())
+            hs.append(h)
+        torch.cuda.synchronize()
+        return hs
+
+    # 1. one launch per op
+    plain = fresh()
+    t0 = time.perf_counter()
+    for h, (_, _, ops) in zip(plain, work):
+        for op in ops:
+            h.apply_op(op)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"[batched] plain launches: {t_plain:.3f} s")
+
+    # 2. captured graphs, one per operator
+    s = torch.cuda.Stream()
+    graphed = fresh()
+    t0 = time.perf_counter()
+    graphs = []
+    for h, (_, _, ops) in zip(graphed, work):
+        h.set_stream(s)
+        ht.capture_begin(s)
+        for op in ops:
+            h.apply_op(op)
+        graphs.append(ht.capture_end(s))
+    t_capture = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in graphs:
+        g.launch(s)
+    s.synchronize()
+    t_graph = time.perf_counter() - t0
+    log(f"[batched] graphs: capture {t_capture:.3f} s, replay {t_graph:.3f} s")
+
+    # 3. one persistent batched launch
+    batched = fresh()
+    batch = ht.Batch(threads=args.threads, wg_per_cu=args.wg_per_cu)
+    t0 = time.perf_counter()
+    for h, (_, _, ops) in zip(batched, work):
+        for op in ops:
+            batch.add_op(h, op)
+    t_build = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"[batched] batch: build {t_build:.3f} s, run {t_batch:.3f} s")
+
+    same_graph = all(torch.equal(a.buffer, b.buffer) for a, b in zip(plain, graphed))
+    same_batch = all(torch.equal(a.buffer, b.buffer) for a, b in zip(plain, batched))
+
+    # oracle on a stratified sample: the first `per_n` operators of each n
+    worst = 0.0
+    checked = 0
+    seen = {}
+    for h, (n, G, ops) in zip(batched, work):
+        if seen.get(n, 0) >= args.per_n:
+            continue
+        seen[n] = seen.get(n, 0) + 1
+        ref = oracle.apply_ops_local(oracle.density_from_factor(G), ops)
+        worst = max(worst, float(np.linalg.norm(h.to_dense() - ref) / np.linalg.norm(ref)))
+        checked += 1
+    out = {
+        "bench": "batched",
+        "operators": args.count, "ops": nops,
+        "tile_log2": args.tile_log2,
+        "plain": {"s": t_plain, "circuits_per_s": args.count / t_plain, "gate_conj_per_s": nops / t_plain},
+        "graph": {"s": t_graph, "capture_s": t_capture, "circuits_per_s": args.count / t_graph,
+                  "gate_conj_per_s": nops / t_graph},
+        "batched": {"s": t_batch, "build_s": t_build, "circuits_per_s": args.count / t_batch,
+                    "gate_conj_per_s": nops / t_batch, "threads": args.threads, "wg_per_cu": args.wg_per_cu},
+        "speedup_vs_plain": t_plain / t_batch, "speedup_vs_graph": t_graph / t_batch,
+        "bitwise_equal": {"graph": same_graph, "batched": same_batch},
+        "oracle_check": {"operators": checked, "max_rel_frobenius": worst, "tolerance": 1e-12},
+        "state": "Ginibre factor of rank min(2^n, 64), normalised",
+    }
+    print(json.dumps(out), flush=True)
+
+
+# -------------------------------------------------------------------- serve
+
+def _serve_stream(ht, reqs, rate_hint, **cfg):
+    srv = ht.Server(**cfg)
+    t_start = srv.now()
+    ids = []
+    for r in reqs:
+        while srv.now() - t_start < r["arrival"]:
+            time.sleep(min(0.001, max(0.0, r["arrival"] - (srv.now() - t_start))))
+        ids.append(srv.submit(r["n"], r["G"], r["ops"], r["pauli"], r["dtype"]))
+    srv.wait_idle(1800)
+    res = {d["id"]: d for d in srv.poll()}
+    err = srv.last_error()
+    srv.close()
+    recs = [res[i] for i in ids]
+    lat = np.array([d["t_done"] - d["t_submit"] for d in recs])
+    span = max(d["t_done"] for d in recs) - min(d["t_submit"] for d in recs)
+    return {
+        "circuits_per_s": len(recs) / span,
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "mean_s": float(lat.mean()), "makespan_s": span, "errors": err,
+        "failed": sum(1 for d in recs if d["status"] != 0),
+    }, [d["value"] for d in recs]
+
+
+def run_serve(args):
+    import torch
+    import paper_2604_15765_amd as ht
+    import synth
+
+    torch.cuda.set_device(0)
+    rates = [float(x) for x in args.rates.split(",")]
+    results = []
+    for rate in rates:
+        reqs = synth.serving_requests(args.count, rate, seed=args.seed)
+        nops = sum(len(r["ops"]) for r in reqs)
+        log(f"[serve] rate {rate}/s: {len(reqs)} requests, {nops} ops, n: "
+            f"{sorted(r['n'] for r in reqs)}")
+        cont, v_cont = _serve_stream(ht, reqs, rate, budget_bytes=args.budget_gb << 30,
+                                     max_active=args.max_active, batch_max_qubits=args.batch_max_qubits,
+                                     medium_max_qubits=args.medium_max_qubits,
+                                     max_medium_active=args.max_medium_active,
+                                     chunk_ops=args.chunk_ops, large_chunk_ops=args.large_chunk_ops)
+        log(f"[serve]   continuous: {cont}")
+        fifo, v_fifo = _serve_stream(ht, reqs, rate, budget_bytes=args.budget_gb << 30, fifo=1)
+        log(f"[serve]   one at a time: {fifo}")
+        results.append({"rate": rate, "requests": len(reqs), "ops": nops, "continuous": cont,
+                        "plain_fifo": fifo, "equal_results": v_cont == v_fifo,
+                        "throughput_ratio": cont["circuits_per_s"] / fifo["circuits_per_s"],
+                        "p99_ratio": fifo["p99_s"] / cont["p99_s"]})
+    print(json.dumps({"bench": "serve", "results": results,
+                      "workload": "Poisson arrivals; n = floor(exp(U(ln 6, ln 17))); 10..300 mixed ops; "
+                                  "c128/c64 50/50; half with a 64-term Pauli-sum readout"}), flush=True)
+
+
+# ---------------------------------------------------------------- precision
+
+def run_precision(args):
+    import torch
+    import oracle
+    import paper_2604_15765_amd as ht
+    import synth
+
+    torch.cuda.set_device(0)
+    out = {"bench": "precision"}
+    # n = 16: throughput and the c64 error against the c128 GPU state
+    n = 16
+    r_state, r_ops, r_obs = synth.spawn_rngs(args.seed, 3)
+    G = synth.ginibre_factor(n, 16, r_state)
+    layers = [synth.layer_n16(l, r_ops, n=n) for l in range(args.layers)]
+    codes, coeffs = synth.random_pauli_sum(n, 64, r_obs)
+    states = {}
+    for dtype in ("c128", "c64"):
+        h = ht.Herm(n, 5, dtype).init_lowrank(G)
+        h.scale(1.0 / h.trace())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cnt = 0
+        for ops in layers:
+            for op in ops:
+                h.apply_op(op)
+            cnt += len(ops)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[dtype] = {"gate_conj_per_s": cnt / dt, "GBps": cnt * 2 * h.nbytes / dt / 1e9,
+                      "trace": h.trace(), "pauli_expectation": h.expectation_pauli_sum(codes, coeffs)}
+        states[dtype] = h
+        log(f"[precision] n=16 {dtype}: {out[dtype]}")
+    rng = synth.make_rng(args.seed + 1)
+    rows = rng.integers(0, 1 << n, size=200000)
+    cols = rng.integers(0, 1 << n, size=200000)
+    a = states["c128"].get_entries(rows, cols)
+    b = states["c64"].get_entries(rows, cols)
+    out["n16_c64_vs_c128"] = {
+        "sampled_entries": int(rows.size),
+        "rel_frobenius_sampled": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
+        "trace_diff": abs(out["c128"]["trace"] - out["c64"]["trace"]),
+        "pauli_expectation_diff": abs(out["c128"]["pauli_expectation"] - out["c64"]["pauli_expectation"]),
+        "passes": sum(len(l) for l in layers),
+        "bound_rel_frobenius": (sum(len(l) for l in layers) + 1) * 2.0 ** -24,
+    }
+    del states
+    torch.cuda.empty_cache()
+    # smaller n: both storage types against the CPU oracle
+    n = args.check_n
+    G = synth.ginibre_factor(n, 16, r_state)
+    lay = [synth.layer_n16(l, r_ops, n=n) for l in range(args.layers)]
+    ops = [op for l in lay for op in l]
+    ref = oracle.apply_ops_local(oracle.density_from_factor(G), ops)
+    errs = {}
+    for dtype in ("c128", "c64"):
+        h = ht.Herm(n, 5, dtype).init_lowrank(G)
+        h.scale(1.0 / h.trace())
+        for op in ops:
+            h.apply_op(op)
+        errs[dtype] = float(np.linalg.norm(h.to_dense() - ref) / np.linalg.norm(ref))
+    out[f"n{n}_vs_oracle"] = {"passes": len(ops), "rel_frobenius": errs,
+                            "bound_c64": (len(ops) + 1) * 2.0 ** -24, "tolerance_c128": 1e-12}
+    out["speedup_c64_over_c128"] = out["c64"]["gate_conj_per_s"] / out["c128"]["gate_conj_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = p.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("batched")
+    b.add_argument("--count", type=int, default=4096)
+    b.add_argument("--seed", type=int, default=4096)
+    b.add_argument("--tile-log2", type=int, default=5)
+    b.add_argument("--threads", type=int, default=256)
+    b.add_argument("--wg-per-cu", type=int, default=2)
+    b.add_argument("--per-n", type=int, default=2, help="operators per n checked against the oracle")
+    s = sub.add_parser("serve")
+    s.add_argument("--rates", default="10,100,1000")
+    s.add_argument("--count", type=int, default=48)
+    s.add_argument("--seed", type=int, default=2000)
+    s.add_argument("--budget-gb", type=int, default=200)
+    s.add_argument("--max-active", type=int, default=32)
+    s.add_argument("--batch-max-qubits", type=int, default=8)
+    s.add_argument("--medium-max-qubits", type=int, default=12)
+    s.add_argument("--max-medium-active", type=int, default=4)
+    s.add_argument("--chunk-ops", type=int, default=64)
+    s.add_argument("--large-chunk-ops", type=int, default=4)
+    r = sub.add_parser("precision")
+    r.add_argument("--layers", type=int, default=4)
+    r.add_argument("--check-n", type=int, default=11, help="qubits of the oracle-checked run")
+    r.add_argument("--seed", type=int, default=1616)
+    args = p.parse_args()
+    {"batched": run_batched, "serve": run_serve, "precision": run_precision}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()

@@ -260,8 +260,9 @@ ht_status ht_graph_destroy(ht_graph* g);
 /* --------------------------------------------------------------- server -- */
 
 /* A request server with continuous batching.  A scheduler thread admits
- * requests first-come first-served when a slot and enough of the HBM budget
- * are free, keeps each operator resident until its readout, advances small
+ * requests first-come first-served (per lane: small and large) when a slot
+ * and enough of the HBM budget are free, keeps each operator resident until
+ * its readout, advances small
  * operators (n <= batch_max_qubits) in rounds of one batched launch each
  * (requests join and leave between rounds) and large ones on their own
  * streams in chunks of plain passes, so the work of different requests
@@ -273,7 +274,7 @@ typedef struct ht_server ht_server;
 typedef struct {
   size_t budget_bytes;   /* HBM for resident operators (and their inputs) */
   int max_active;        /* requests resident at once, 1..256 */
-  int batch_max_qubits;  /* n <= this: batched path; larger: plain passes */
+  int batch_max_qubits;  /* n <= this: batched rounds; larger: plain passes */
   int chunk_ops;         /* ops per small request per batched round */
   int large_chunk_ops;   /* ops per chunk of a large request */
   int tile_log2;         /* tile edge exponent of every operator */
@@ -281,10 +282,18 @@ typedef struct {
   int batch_threads;     /* see ht_batch_set_param */
   int batch_wg_per_cu;
   size_t lds_max_bytes;
+  int max_large_active;  /* large requests running passes at once */
+  int medium_max_qubits; /* n <= this (and > batch_max_qubits): medium lane */
+  int max_medium_active; /* medium requests running passes at once */
 } ht_server_config;
 
-/* Defaults: 200 GiB budget, 32 active, batched up to n = 11, 64 ops per
- * round, 4 ops per large chunk, tile edge 32, continuous batching. */
+/* Defaults: 200 GiB budget, 32 active, batched rounds up to n = 8 (an
+ * operator a single workgroup evolves from cache), medium lane up to n = 12
+ * with 4 at once (their passes do not fill the GPU alone), large requests one
+ * at a time (a large pass saturates HBM on its own; two at once only make
+ * their access streams compete); 64 ops per round, 4 ops per chunk, tile
+ * edge 32.  Each plain-pass lane also admits one request ahead of its limit
+ * so that its initial state is built while the others run. */
 void ht_server_config_default(ht_server_config* cfg);
 
 /* A request: initial state G G^dagger / tr(G G^dagger) for the host N x rank

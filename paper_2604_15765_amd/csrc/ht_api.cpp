@@ -187,10 +187,6 @@ ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, si
     h->out_dev = nullptr;
     return cleanup(ht_fail(HT_ENOMEM, "could not allocate result buffer"));
   }
-  if (hipHostMalloc(&h->out_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    h->out_host = nullptr;
-    return cleanup(ht_fail(HT_ENOMEM, "could not allocate pinned result buffer"));
-  }
   *out = h;
   return HT_OK;
 }
@@ -207,7 +203,6 @@ ht_status ht_herm_destroy(ht_herm* h) {
   if (h->owned && h->buf) (void)hipFree(h->buf);
   if (h->coef_dev) (void)hipFree(h->coef_dev);
   if (h->out_dev) (void)hipFree(h->out_dev);
-  if (h->out_host) (void)hipHostFree(h->out_host);
   if (h->red) (void)hipFree(h->red);
   if (h->tmp) (void)hipFree(h->tmp);
   delete h;

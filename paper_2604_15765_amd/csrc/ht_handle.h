@@ -37,7 +37,7 @@ struct ht_herm {
   // device scratch
   double* coef_dev = nullptr;   // 512 doubles: two-qubit transfer matrices
   double* out_dev = nullptr;    // 8 doubles: reduction results
-  double* out_host = nullptr;   // pinned: 8 doubles
+  double out_host[8] = {};      // host copy of a reduction result
   double* red = nullptr;        // reduction partial sums
   size_t red_cap = 0;           // doubles
   void* tmp = nullptr;          // term tables and other per-call uploads

@@ -132,6 +132,45 @@ __global__ void unpack_dense_kernel(const S2<T>* __restrict__ h, uint64_t N, int
   }
 }
 
+// H = G G^dagger, one workgroup per tile (grid-stride).  The M rows of G
+// that the tile's rows and columns need are staged in LDS transposed
+// ([r][row]), so the lanes of a wave (consecutive columns) read consecutive
+// LDS words.  Used when 2 M rank complex values fit the LDS budget.
+template <typename T>
+__global__ void __launch_bounds__(256) lowrank_lds_kernel(S2<T>* __restrict__ h, uint64_t ntiles,
+                                                          int m, const double* __restrict__ G,
+                                                          int rank) {
+  extern __shared__ __align__(16) double lds[];
+  const uint32_t M = 1u << m;
+  double2* gi = reinterpret_cast<double2*>(lds);  // [rank][M]
+  double2* gj = gi + (size_t)rank * M;            // [rank][M]
+  const uint32_t MM = M * M;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t ti, tj;
+    tri_decode(t, ti, tj);
+    ti = wave_uniform(ti);
+    tj = wave_uniform(tj);
+    __syncthreads();  // the previous tile's reads are done
+    for (uint32_t e = threadIdx.x; e < M * (uint32_t)rank; e += blockDim.x) {
+      const uint32_t row = e / rank, r = e % rank;
+      const uint64_t gr = ((uint64_t)ti << m) + row, gc = ((uint64_t)tj << m) + row;
+      gi[(size_t)r * M + row] = make_double2(G[2 * (gr * rank + r)], G[2 * (gr * rank + r) + 1]);
+      gj[(size_t)r * M + row] = make_double2(G[2 * (gc * rank + r)], G[2 * (gc * rank + r) + 1]);
+    }
+    __syncthreads();
+    S2<T>* tile = h + (t << (2 * m));
+    for (uint32_t e = threadIdx.x; e < MM; e += blockDim.x) {
+      const uint32_t i = e >> m, j = e & (M - 1);
+      cd acc = {0.0, 0.0};
+      for (int r = 0; r < rank; ++r) {
+        const double2 a = gi[(size_t)r * M + i], b = gj[(size_t)r * M + j];
+        acc = cfma_cj(acc, cd{a.x, a.y}, cd{b.x, b.y});
+      }
+      store_c<T>(tile, e, acc);
+    }
+  }
+}
+
 template <typename T>
 __global__ void lowrank_kernel(S2<T>* __restrict__ h, uint64_t ntiles, int m,
                                const double* __restrict__ G, int rank) {
@@ -404,6 +443,16 @@ hipError_t launch_unpack_dense(int dtype, const void* buf, int n, int m, double*
 hipError_t launch_lowrank(int dtype, void* buf, int n, int m, const double* G, int rank,
                           hipStream_t s) {
   const uint64_t nt = ntiles_of(n, m);
+  const size_t lds = (size_t)2 * ((size_t)1 << m) * (size_t)rank * sizeof(double2);
+  if (lds <= 64 * 1024) {
+    const unsigned g = grid_for(nt, 1, 8192);
+    HT_DT_DISPATCH(dtype,
+                   hipLaunchKernelGGL(lowrank_lds_kernel<double>, dim3(g), dim3(kThreads), lds, s,
+                                      reinterpret_cast<S2<double>*>(buf), nt, m, G, rank),
+                   hipLaunchKernelGGL(lowrank_lds_kernel<float>, dim3(g), dim3(kThreads), lds, s,
+                                      reinterpret_cast<S2<float>*>(buf), nt, m, G, rank));
+    return hipGetLastError();
+  }
   const unsigned g = grid_for(nt, kThreads / 64, 8192);
   HT_DT_DISPATCH(dtype,
                  hipLaunchKernelGGL(lowrank_kernel<double>, dim3(g), dim3(kThreads), 0, s,

@@ -57,7 +57,8 @@ struct Req {
   size_t next = 0;  // first op not yet enqueued
   void* gbuf = nullptr;  // device copy of G, released after the initial state is built
   size_t gbytes = 0;
-  bool large = false;
+  int lane = 0;          // 0: batched rounds, 1: medium, 2: large (plain passes)
+  bool large = false;    // lane > 0: runs plain passes on its slot's stream
   int chunks_in_flight = 0;  // large path: chunks enqueued and not yet seen complete (<= 2)
   int chunk_ev = 0;          // event slot the next chunk records
 };
@@ -101,7 +102,7 @@ struct ht_server {
   std::atomic<bool> stop{false};
 
   // scheduler thread only
-  std::deque<std::unique_ptr<Req>> pending;
+  std::deque<std::unique_ptr<Req>> pending[3];  // per lane, arrival order
   std::vector<std::unique_ptr<Req>> active;
   std::vector<Slot> slots;
   std::vector<int> free_slots;
@@ -239,6 +240,38 @@ void fail_request(ht_server* s, std::unique_ptr<Req>& rp, hipError_t e) {
   finish(s, rp);
 }
 
+// Admit the request at the front of `pending` if a slot and its memory are
+// available (false: it has to wait).  A request whose initialisation cannot
+// be enqueued fails and is reported; the call still returns true.
+bool admit_front(ht_server* s, std::deque<std::unique_ptr<Req>>& pending) {
+  if (s->free_slots.empty()) return false;
+  Req* r = pending.front().get();
+  void* buf = take_buffer(s, r->bytes);
+  if (!buf) return false;
+  void* gbuf = take_buffer(s, r->gbytes);
+  if (!gbuf) {
+    give_buffer(s, buf, r->bytes);
+    return false;
+  }
+  std::unique_ptr<Req> rp = std::move(pending.front());
+  pending.pop_front();
+  r->buf = buf;
+  r->gbuf = gbuf;
+  r->slot = s->free_slots.back();
+  s->free_slots.pop_back();
+  Slot& sl = s->slots[r->slot];
+  sl.req = r;
+  r->t_admit = s->now();
+  hipError_t e = start_request(r, sl);
+  if (e != hipSuccess) {
+    fail_request(s, rp, e);
+    return true;
+  }
+  r->state = INIT;
+  s->active.push_back(std::move(rp));
+  return true;
+}
+
 void scheduler(ht_server* s) {
   (void)hipSetDevice(s->device);
   const bool fifo = s->cfg.fifo != 0;
@@ -247,50 +280,47 @@ void scheduler(ht_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       while (!s->inbox.empty()) {
-        s->pending.push_back(std::move(s->inbox.front()));
+        std::unique_ptr<Req>& q = s->inbox.front();
+        q->lane = fifo ? 2 : q->n <= s->cfg.batch_max_qubits ? 0 : q->n <= s->cfg.medium_max_qubits ? 1 : 2;
+        q->large = q->lane > 0;
+        s->pending[q->lane].push_back(std::move(q));
         s->inbox.pop_front();
         progressed = true;
       }
     }
-    if (s->stop.load() && s->pending.empty() && s->active.empty()) break;
+    if (s->stop.load() && s->pending[0].empty() && s->pending[1].empty() && s->pending[2].empty() &&
+        s->active.empty())
+      break;
+    const int lane_limit[3] = {s->cfg.max_active, s->cfg.max_medium_active, s->cfg.max_large_active};
 
-    // admission, first come first served
-    while (!s->pending.empty() && !s->free_slots.empty()) {
-      Req* r = s->pending.front().get();
-      void* buf = take_buffer(s, r->bytes);
-      if (!buf) break;  // wait for memory to free up
-      void* gbuf = take_buffer(s, r->gbytes);
-      if (!gbuf) {
-        give_buffer(s, buf, r->bytes);
-        break;
+    // admission: first come first served within each lane.  The plain-pass
+    // lanes admit up to their concurrency limit plus one request that builds
+    // its initial state ahead.
+    int admitted[3] = {0, 0, 0};
+    for (const auto& a : s->active) ++admitted[a->lane];
+    for (int lane = 0; lane < 3; ++lane) {
+      const int cap = lane == 0 ? s->cfg.max_active : lane_limit[lane] + 1;
+      while (!s->pending[lane].empty() && admitted[lane] < cap && admit_front(s, s->pending[lane])) {
+        ++admitted[lane];
+        progressed = true;
       }
-      std::unique_ptr<Req> rp = std::move(s->pending.front());
-      s->pending.pop_front();
-      r->buf = buf;
-      r->gbuf = gbuf;
-      r->slot = s->free_slots.back();
-      s->free_slots.pop_back();
-      Slot& sl = s->slots[r->slot];
-      sl.req = r;
-      r->t_admit = s->now();
-      r->large = fifo || r->n > s->cfg.batch_max_qubits;
-      hipError_t e = start_request(r, sl);
-      if (e != hipSuccess) {
-        fail_request(s, rp, e);
-        continue;
-      }
-      r->state = INIT;
-      s->active.push_back(std::move(rp));
-      progressed = true;
     }
 
-    // per-request progress: init done, large chunks, readouts
+    // per-request progress: init done, chunks, readouts.  `active` is in
+    // admission order; in each plain-pass lane only the oldest requests up to
+    // the lane's concurrency limit that still have ops to run enqueue chunks.
     std::vector<Req*> batch_ready;
+    int lane_rank[3] = {0, 0, 0};
     for (size_t i = 0; i < s->active.size();) {
       Req* r = s->active[i].get();
       Slot& sl = s->slots[r->slot];
       hipError_t e = hipSuccess;
       bool finished = false;
+      bool may_run = true;
+      if (r->large && (r->state == INIT || r->state == RUN)) {
+        may_run = lane_rank[r->lane] < lane_limit[r->lane];
+        ++lane_rank[r->lane];
+      }
       if (r->state == INIT) {
         hipError_t q = hipEventQuery(sl.ev_init);
         if (q == hipSuccess) {
@@ -315,14 +345,14 @@ void scheduler(ht_server* s) {
           }
         }
         // keep up to two chunks queued; the readout follows the last one
-        if (e == hipSuccess && r->chunks_in_flight < 2 && r->next < r->ops.size()) {
+        if (e == hipSuccess && may_run && r->chunks_in_flight < 2 && r->next < r->ops.size()) {
           e = enqueue_chunk(s, r, sl, (size_t)s->cfg.large_chunk_ops);
           if (e == hipSuccess && r->next >= r->ops.size()) {
             e = enqueue_readout(r, sl, sl.stream);
             r->state = READOUT;
           }
           progressed = true;
-        } else if (e == hipSuccess && r->ops.empty()) {
+        } else if (e == hipSuccess && may_run && r->ops.empty()) {
           e = enqueue_readout(r, sl, sl.stream);
           r->state = READOUT;
           progressed = true;
@@ -403,7 +433,6 @@ void ht_server_config_default(ht_server_config* c) {
   if (!c) return;
   c->budget_bytes = (size_t)200 << 30;
   c->max_active = 32;
-  c->batch_max_qubits = 11;
   c->chunk_ops = 64;
   c->large_chunk_ops = 4;
   c->tile_log2 = 5;
@@ -411,6 +440,10 @@ void ht_server_config_default(ht_server_config* c) {
   c->batch_threads = 256;
   c->batch_wg_per_cu = 2;
   c->lds_max_bytes = 65536;
+  c->max_large_active = 1;
+  c->batch_max_qubits = 8;
+  c->medium_max_qubits = 12;
+  c->max_medium_active = 4;
 }
 
 ht_status ht_server_create(const ht_server_config* cfg, ht_server** out) {
@@ -422,6 +455,8 @@ ht_status ht_server_create(const ht_server_config* cfg, ht_server** out) {
     return ht_fail(HT_EINVAL, "chunk sizes must be positive");
   if (cfg->tile_log2 < HT_MIN_TILE_LOG2 || cfg->tile_log2 > HT_MAX_TILE_LOG2)
     return ht_fail(HT_EINVAL, "tile_log2 out of range");
+  if (cfg->max_large_active < 1 || cfg->max_medium_active < 1)
+    return ht_fail(HT_EINVAL, "lane concurrency limits must be positive");
   ht_server* s = new ht_server();
   s->cfg = *cfg;
   if (s->cfg.fifo) s->cfg.max_active = 1;

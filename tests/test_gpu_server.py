@@ -52,7 +52,7 @@ def _oracle_value(r):
 
 def test_server_results_alone_mix_and_fifo(ht):
     reqs = _requests(77, 26, [3, 4, 5, 6, 7, 8, 9]) + _requests(78, 2, [12, 13])
-    cfg = dict(batch_max_qubits=11, chunk_ops=16, large_chunk_ops=3)
+    cfg = dict(batch_max_qubits=7, medium_max_qubits=9, chunk_ops=16, large_chunk_ops=3)
     alone, _ = _serve(ht, [reqs[0]], **cfg)
     mixed, recs = _serve(ht, reqs, **cfg)
     fifo, _ = _serve(ht, reqs, fifo=1)
