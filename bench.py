@@ -181,6 +181,12 @@ def main():
     classes = {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
                    "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in sorted(prof.items())}
     kernel_ms = sum(v["ms"] for v in prof.values())
+    # HBM bytes per launch of the dominant class from the committed rocprofv3
+    # counter summary, if it was taken with the current kernel sources
+    from paper_2604_15765_amd.profile_summary import read_traffic
+    counted = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                        f"conj_n{n}_{args.dtype}_counters.txt"))
+    traffic = counted.get(dom_name) if counted else None
     out = {
         "metric": METRIC,
         "value": nops / elapsed,
@@ -211,7 +217,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": dom_avg_ms,
             "bytes_per_launch": per_op_bytes,
         },

@@ -362,8 +362,9 @@ const char* ht_kernel_class_name(int idx);
 /* Launch tuning of the conjugation pass, process-wide; it changes speed, never
  * results.  "conj_wg_per_cu" (1..64, default 8): workgroups per compute unit
  * of the grid-stride grid.  "conj_block_threads" (64, 128 or 256, default
- * 256): workgroup size.  "conj_mem_mode" (0..3, default 0): bit 0 marks the
- * pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
+ * 256): workgroup size.  "conj_mem_mode" (-1..3, default -1 = automatic:
+ * nontemporal loads and stores when every store writes whole cache lines);
+ * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
  * 0): 0 = each wave processes whole tile groups, 1 = the patches of a group
  * are spread over neighbouring waves.  HT_EINVAL for an unknown name or value. */
 ht_status ht_set_tuning(const char* name, int64_t value);

@@ -5,6 +5,7 @@
 Outputs, next to this file:
     libhermtile.so   the C-ABI library (include/hermtile.h)
     _hostcheck.so    test support: the conjugation lane body run on the CPU
+    _probe.so        measurement tool: HBM streaming probe (stream_probe.py)
 """
 
 from __future__ import annotations
@@ -32,6 +33,7 @@ LIB_SOURCES = ["ht_conj.hip", "ht_misc.hip", "ht_batch.hip", "ht_api.cpp", "ht_b
                "ht_batch_runner.cpp", "ht_server.cpp", "ht_prep.cpp"]
 LIB = os.path.join(HERE, "libhermtile.so")
 HOSTCHECK = os.path.join(HERE, "_hostcheck.so")
+PROBE = os.path.join(HERE, "_probe.so")
 
 
 def _run(cmd, verbose):
@@ -66,6 +68,10 @@ def build(verbose: bool = False) -> None:
           os.path.join(CSRC, "ht_hostcheck.cpp"), "-x", "c++", os.path.join(CSRC, "ht_prep.cpp"),
           "-o", tmp], verbose)
     os.replace(tmp, HOSTCHECK)
+    tmp = PROBE + ".tmp"
+    _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-shared", os.path.join(CSRC, "ht_probe.hip"), "-o", tmp],
+         verbose)
+    os.replace(tmp, PROBE)
 
 
 if __name__ == "__main__":

@@ -568,7 +568,7 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     return HT_OK;
   }
   if (k == "conj_mem_mode") {
-    if (value < 0 || value > 3) return ht_fail(HT_EINVAL, "conj_mem_mode must be in [0, 3]");
+    if (value < -1 || value > 3) return ht_fail(HT_EINVAL, "conj_mem_mode must be in [-1, 3]");
     ht::tuning().mem_mode = (int)value;
     return HT_OK;
   }

@@ -72,7 +72,15 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
-  switch (tuning().mem_mode) {
+  int mode = tuning().mem_mode;
+  if (mode < 0) {
+    // Nontemporal hints pay off only when every store instruction writes
+    // whole 128-byte lines: 16-byte entries and no intra target below bit 3
+    // (a lower column target splits the 8 lanes of a row across two lines).
+    constexpr int KI = K - C;
+    mode = (sizeof(T) == 8 && (KI == 0 || g.ipos[0] >= 3)) ? 3 : 0;
+  }
+  switch (mode) {
     case 1:
       hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 1>), dim3((unsigned)wgs), dim3(threads), 0, s,
                          hp, g, cf, coef_dev, tuning().order);

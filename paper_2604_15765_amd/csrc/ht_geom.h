@@ -99,6 +99,11 @@ HT_HD void tri_decode(uint64_t g, uint32_t& ti, uint32_t& tj) {
   tj = (uint32_t)(g - tri64(t));
 }
 
+// Blocks in flight per lane: 16 entry loads for k = 1 (4 blocks) and for
+// k = 2 (one block) -- the depth at which an in-place stream on MI355X
+// reaches its best bandwidth.
+constexpr int conj_unroll(int K) { return K == 1 ? 4 : 1; }
+
 // Geometry of one conjugation pass with K targets of which C are cross.
 template <int K, int C>
 struct ConjGeom {
@@ -372,11 +377,6 @@ HT_HD void block_update_store(const Mem& mem, const ConjGeom<K, C>& g, const Gro
     }
   });
 }
-
-// Blocks in flight per lane: 16 entry loads for k = 1 (4 blocks) and for
-// k = 2 (one block) -- the depth at which an in-place stream on MI355X
-// reaches its best bandwidth.
-constexpr int conj_unroll(int K) { return K == 1 ? 4 : 1; }
 
 // All blocks one lane owns in the current group: patches of 64 blocks, JU
 // patches per step, every load of a step issued before any update (JU

@@ -18,7 +18,7 @@ inline int conj_class(int k, int c, int form) { return (k == 1 ? 0 : 4) + c * 2 
 struct LaunchTuning {
   int block_threads = 256;  // 4 waves per workgroup
   int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
-  int mem_mode = 0;         // bit 0: nontemporal loads, bit 1: nontemporal stores
+  int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
   int order = 0;            // 0: a wave walks a whole group; 1: waves share a group's patches
 };
 LaunchTuning& tuning();
