@@ -60,10 +60,10 @@ def run_batched(args):
 
     G_dev = [torch.from_numpy(G).to("cuda") for _, G, _ in work]
 
-    def fresh():
+    def fresh(edges=tile):
         hs = []
         for (n, _, _), g in zip(work, G_dev):
-            h = ht.Herm(n, tile[n]).init_lowrank(g)
+            h = ht.Herm(n, edges[n]).init_lowrank(g)
             h.scale(1.0 / h.trace())
             hs.append(h)
         torch.cuda.synchronize()
@@ -116,17 +116,47 @@ def run_batched(args):
 
     same_graph = all(torch.equal(a.buffer, b.buffer) for a, b in zip(plain, graphed))
     same_batch = all(torch.equal(a.buffer, b.buffer) for a, b in zip(plain, batched))
+    del graphs, graphed
+
+    # 4. autotuned: tile edge per n and launch shape picked on a sample of the
+    # queued batch, operators created with the chosen edges
+    tuned_cfg = batch.autotune(args.tune_sample)
+    log(f"[batched] autotune: {tuned_cfg}")
+    edges = dict(tile)
+    edges.update(tuned_cfg["tile_log2"])
+    del plain
+    tplain = fresh(edges)
+    t0 = time.perf_counter()
+    for h, (_, _, ops) in zip(tplain, work):
+        for op in ops:
+            h.apply_op(op)
+    torch.cuda.synchronize()
+    t_tplain = time.perf_counter() - t0
+    tuned = fresh(edges)
+    tbatch = ht.Batch(threads=tuned_cfg["threads"], wg_per_cu=tuned_cfg["wg_per_cu"],
+                      lds_max_bytes=tuned_cfg["lds_max_bytes"])
+    for h, (_, _, ops) in zip(tuned, work):
+        for op in ops:
+            tbatch.add_op(h, op)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tbatch.run()
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - t0
+    log(f"[batched] tuned edges, plain launches: {t_tplain:.3f} s; tuned batch: {t_tuned:.3f} s")
+    same_tuned = all(torch.equal(a.buffer, b.buffer) for a, b in zip(tplain, tuned))
 
     # oracle on a stratified sample: the first `per_n` operators of each n
     worst = 0.0
     checked = 0
     seen = {}
-    for h, (n, G, ops) in zip(batched, work):
+    for h, ht_, (n, G, ops) in zip(batched, tuned, work):
         if seen.get(n, 0) >= args.per_n:
             continue
         seen[n] = seen.get(n, 0) + 1
         ref = oracle.apply_ops_local(oracle.density_from_factor(G), ops)
-        worst = max(worst, float(np.linalg.norm(h.to_dense() - ref) / np.linalg.norm(ref)))
+        for x in (h, ht_):
+            worst = max(worst, float(np.linalg.norm(x.to_dense() - ref) / np.linalg.norm(ref)))
         checked += 1
     out = {
         "bench": "batched",
@@ -137,8 +167,12 @@ def run_batched(args):
                   "gate_conj_per_s": nops / t_graph},
         "batched": {"s": t_batch, "build_s": t_build, "circuits_per_s": args.count / t_batch,
                     "gate_conj_per_s": nops / t_batch, "threads": args.threads, "wg_per_cu": args.wg_per_cu},
+        "tuned": {"s": t_tuned, "plain_s": t_tplain, "circuits_per_s": args.count / t_tuned,
+                  "gate_conj_per_s": nops / t_tuned, "autotune": tuned_cfg,
+                  "speedup_vs_plain_same_edges": t_tplain / t_tuned,
+                  "speedup_vs_plain_default_edges": t_plain / t_tuned},
         "speedup_vs_plain": t_plain / t_batch, "speedup_vs_graph": t_graph / t_batch,
-        "bitwise_equal": {"graph": same_graph, "batched": same_batch},
+        "bitwise_equal": {"graph": same_graph, "batched": same_batch, "tuned_vs_plain": same_tuned},
         "oracle_check": {"operators": checked, "max_rel_frobenius": worst, "tolerance": 1e-12},
         "state": "Ginibre factor of rank min(2^n, 64), normalised",
     }
@@ -277,6 +311,7 @@ def main():
     b.add_argument("--threads", type=int, default=256)
     b.add_argument("--wg-per-cu", type=int, default=2)
     b.add_argument("--per-n", type=int, default=2, help="operators per n checked against the oracle")
+    b.add_argument("--tune-sample", type=int, default=512, help="operators the autotuner times")
     s = sub.add_parser("serve")
     s.add_argument("--rates", default="10,100,1000")
     s.add_argument("--count", type=int, default=48)

@@ -222,8 +222,9 @@ ht_status ht_batch_destroy(ht_batch* b);
 
 /* Schedule parameters: "threads" (64..1024, power of two, default 256) per
  * workgroup; "wg_per_cu" (1..32, default 2) workgroups per compute unit;
- * "lds_max_bytes" (0..163840, default 65536): operators up to this size run
- * in LDS (0 disables LDS staging).  HT_EINVAL for an unknown name or value. */
+ * "lds_max_bytes" (0..163584 = 160 KiB less the kernel's own LDS, default
+ * 65536): operators up to this size run in LDS (0 disables LDS staging).
+ * HT_EINVAL for an unknown name or value. */
 ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value);
 
 /* Queue one op for operator h; arguments as ht_apply_unitary /
@@ -242,6 +243,36 @@ ht_status ht_batch_size(const ht_batch* b, int64_t* noperators, int64_t* nops);
  * first.  The queue is kept: ht_batch_clear empties it. */
 ht_status ht_batch_run(ht_batch* b, void* hip_stream);
 ht_status ht_batch_clear(ht_batch* b);
+
+/* Autotuner of batched launches (the tile edge 2^b is a free parameter of
+ * the tiled format, Section III-B; here it is picked per qubit count by
+ * measurement, together with the launch shape).  Times candidates on a
+ * sample of the queued batch: at most sample_operators operators (0 = 512),
+ * stratified by qubit count and storage type, as zero-initialised scratch
+ * copies evolved by their own queued ops (re-prepared for each candidate
+ * edge; run time does not depend on the values).  Searches, in turn: per
+ * qubit count n, tile exponents 2..min(n, 7) and the operators' own; launch
+ * shapes threads x wg_per_cu (at most 2048 threads per compute unit) x
+ * lds_max_bytes in {0, 65536, 163584}; then the tile exponents again at the
+ * chosen shape.  The fastest shape is stored in the batch (as by
+ * ht_batch_set_param).  The queued operators are not changed: an operator's
+ * tile edge is fixed when it is created, so to use the chosen edges create
+ * the operators with out->tile_log2[n] and queue the ops again.
+ * Synchronous.  Scratch: the sample's storage at one set of edges, from
+ * hipMalloc on the batch's device; HT_ENOMEM if that exceeds half the free
+ * device memory.  HT_EINVAL for an empty batch or a NULL argument. */
+typedef struct {
+  int tile_log2[HT_MAX_QUBITS + 1]; /* chosen exponent per qubit count; 0 where none */
+  int threads;                      /* chosen launch shape (stored in the batch) */
+  int wg_per_cu;
+  int64_t lds_max_bytes;
+  int sample_operators;             /* operators in the timed sample */
+  int configs_timed;                /* candidate configurations timed */
+  double sample_seconds_before;     /* sample at the queued edges and the batch's former shape */
+  double sample_seconds_after;      /* sample at the chosen edges and shape */
+  double tuning_seconds;            /* wall time of the whole search */
+} ht_batch_tuning;
+ht_status ht_batch_autotune(ht_batch* b, int sample_operators, ht_batch_tuning* out);
 
 /* --------------------------------------------------------------- graphs -- */
 

@@ -96,6 +96,7 @@ def _load():
         "ht_batch_size": (c_int, [vp, P(c_int64), P(c_int64)]),
         "ht_batch_run": (c_int, [vp, vp]),
         "ht_batch_clear": (c_int, [vp]),
+        "ht_batch_autotune": (c_int, [vp, c_int, vp]),
         "ht_capture_begin": (c_int, [vp]),
         "ht_capture_end": (c_int, [vp, P(vp)]),
         "ht_graph_launch": (c_int, [vp, vp]),
@@ -366,6 +367,25 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+MAX_QUBITS = 18  # HT_MAX_QUBITS
+
+
+class BatchTuning(ctypes.Structure):
+    """ht_batch_tuning (field order as in include/hermtile.h)."""
+
+    _fields_ = [
+        ("tile_log2", ctypes.c_int * (MAX_QUBITS + 1)),
+        ("threads", ctypes.c_int),
+        ("wg_per_cu", ctypes.c_int),
+        ("lds_max_bytes", ctypes.c_int64),
+        ("sample_operators", ctypes.c_int),
+        ("configs_timed", ctypes.c_int),
+        ("sample_seconds_before", ctypes.c_double),
+        ("sample_seconds_after", ctypes.c_double),
+        ("tuning_seconds", ctypes.c_double),
+    ]
+
+
 class Batch:
     """ht_batch: ops for many operators, executed in one persistent launch."""
 
@@ -412,6 +432,23 @@ class Batch:
     def clear(self) -> None:
         _check(lib.ht_batch_clear(self._b))
         self._keep = {}
+
+    def autotune(self, sample_operators: int = 0) -> dict:
+        """ht_batch_autotune; returns the chosen tile exponent per qubit count
+        ({n: tile_log2}) and launch shape, and the sample's timings."""
+        t = BatchTuning()
+        _check(lib.ht_batch_autotune(self._b, int(sample_operators), ctypes.addressof(t)))
+        return {
+            "tile_log2": {n: t.tile_log2[n] for n in range(MAX_QUBITS + 1) if t.tile_log2[n]},
+            "threads": t.threads,
+            "wg_per_cu": t.wg_per_cu,
+            "lds_max_bytes": t.lds_max_bytes,
+            "sample_operators": t.sample_operators,
+            "configs_timed": t.configs_timed,
+            "sample_seconds_before": t.sample_seconds_before,
+            "sample_seconds_after": t.sample_seconds_after,
+            "tuning_seconds": t.tuning_seconds,
+        }
 
     def close(self) -> None:
         if getattr(self, "_b", None):

@@ -11,21 +11,8 @@
 #include "ht_handle.h"
 #include "ht_internal.h"
 #include "ht_batch_runner.h"
+#include "ht_batch_state.h"
 #include "ht_prep.h"
-
-struct ht_batch {
-  struct Entry {
-    ht_herm* h;
-    std::vector<ht::BatchOp> ops;
-    std::vector<double> coefs;
-  };
-  std::vector<Entry> entries;
-  std::unordered_map<ht_herm*, size_t> index;
-  int device = 0;
-  int num_cu = 256;
-  ht::BatchSchedule sched;
-  ht::BatchRunner runner;
-};
 
 struct ht_graph {
   hipGraph_t graph = nullptr;
@@ -54,23 +41,23 @@ ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, cons
       b->num_cu = h->num_cu;
     }
     e = b->entries.size();
-    b->entries.push_back({h, {}, {}});
+    b->entries.push_back({h, {}, {}, {}, {}});
     b->index[h] = e;
   } else {
     e = it->second;
   }
   auto& en = b->entries[e];
-  ht::BatchOp bo{};
-  bo.k = op.k;
-  bo.ncross = op.ncross;
-  bo.form = op.form;
-  bo.sorted[0] = op.sorted[0];
-  bo.sorted[1] = op.k > 1 ? op.sorted[1] : 0;
-  bo.coef_off = (uint32_t)en.coefs.size();
-  const int D = 1 << op.k;
-  const int nd = 2 * (op.form == 0 ? D * D : D * D * D * D);
-  en.coefs.insert(en.coefs.end(), op.coef, op.coef + nd);
-  en.ops.push_back(bo);
+  ht::append_batch_op(op, en.ops, en.coefs);
+  const int D = 1 << k;
+  ht_batch::RawOp raw{};
+  raw.k = k;
+  raw.targets[0] = targets[0];
+  raw.targets[1] = k > 1 ? targets[1] : 0;
+  raw.r = r;
+  raw.heisenberg = picture == HT_HEISENBERG ? 1 : 0;
+  raw.mat_off = en.mats.size();
+  en.mats.insert(en.mats.end(), mats, mats + (size_t)2 * r * D * D);
+  en.raw.push_back(raw);
   return HT_OK;
 }
 
@@ -102,7 +89,8 @@ ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value) {
     if (value < 1 || value > 32) return ht_fail(HT_EINVAL, "wg_per_cu must be in [1, 32]");
     b->sched.wg_per_cu = (int)value;
   } else if (k == "lds_max_bytes") {
-    if (value < 0 || value > 160 * 1024) return ht_fail(HT_EINVAL, "lds_max_bytes must be in [0, 163840]");
+    if (value < 0 || value > kBatchLdsMax)
+      return ht_fail(HT_EINVAL, "lds_max_bytes must be in [0, %lld]", (long long)kBatchLdsMax);
     b->sched.lds_max = (size_t)value;
   } else {
     return ht_fail(HT_EINVAL, "unknown batch parameter '%s'", name);

@@ -122,3 +122,28 @@ def test_tuning_validation(ht):
 def test_kernel_class_names(ht):
     names = ht.kernel_class_names()
     assert len(names) == 20 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k2_c2_transfer"
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a host C program."""
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "hermtile.h"\n'
+                   f'int main(void) {{\n  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("pyname,cname", [("ServerConfig", "ht_server_config"),
+                                          ("_Request", "ht_request"),
+                                          ("BatchTuning", "ht_batch_tuning")])
+def test_ctypes_structs_match_the_header(ht, pyname, cname, tmp_path):
+    cls = getattr(ht, pyname)
+    fields = [f[0] for f in cls._fields_]
+    size, offsets = _c_layout(cname, fields, tmp_path)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offsets

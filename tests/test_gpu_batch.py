@@ -126,3 +126,64 @@ def test_graph_replays_match_eager(ht):
         s.synchronize()
         assert np.array_equal(h.read_raw(), expect), rep
     g.close()
+
+
+def test_autotune_picks_valid_settings_and_results_stay_exact(ht):
+    """The autotuner returns a tile exponent for every qubit count present
+    (and none for the others) and a valid launch shape; operators created
+    with the chosen edges and run as one batch at the chosen shape give
+    bitwise the storage of one launch per op, and match the oracle.  The
+    operators queued for tuning are left untouched."""
+    rng = synth.make_rng(1200)
+    cases = []
+    for i in range(36):
+        n = int(rng.integers(3, 9))
+        dtype = "c64" if i % 6 == 5 else "c128"
+        cases.append((n, dtype, synth.random_hermitian_dense(n, rng), _random_circuit(n, int(rng.integers(5, 25)), rng)))
+    tune = ht.Batch()
+    probes = []
+    for n, dtype, H, ops in cases:
+        h = ht.Herm(n, 5, dtype).init_dense(H)
+        for op in ops:
+            tune.add_op(h, op)
+        probes.append((h, h.read_raw().copy()))
+    res = tune.autotune()
+    present = sorted({c[0] for c in cases})
+    assert sorted(res["tile_log2"]) == present
+    for n, m in res["tile_log2"].items():
+        assert 1 <= m <= min(n, 7) or m == min(n, 5), (n, m)
+    assert res["threads"] in (256, 512, 1024) and res["wg_per_cu"] in (1, 2, 4, 8)
+    assert res["threads"] * res["wg_per_cu"] <= 2048
+    assert res["lds_max_bytes"] in (0, 65536, 163584)
+    assert res["sample_operators"] == len(cases) and res["configs_timed"] > 0
+    assert res["sample_seconds_after"] > 0 and res["tuning_seconds"] > 0
+    for h, raw in probes:  # tuning evolves scratch copies only
+        assert np.array_equal(h.read_raw(), raw)
+    tune.close()
+
+    batch = ht.Batch(threads=res["threads"], wg_per_cu=res["wg_per_cu"],
+                     lds_max_bytes=res["lds_max_bytes"])
+    pairs = []
+    for n, dtype, H, ops in cases:
+        m = res["tile_log2"][n]
+        a = ht.Herm(n, m, dtype).init_dense(H)
+        b = ht.Herm(n, m, dtype).init_dense(H)
+        for op in ops:
+            batch.add_op(a, op)
+            b.apply_op(op)
+        pairs.append((a, b, H, ops, dtype))
+    batch.run()
+    torch.cuda.synchronize()
+    for a, b, H, ops, dtype in pairs:
+        assert np.array_equal(a.read_raw(), b.read_raw()), (a.n, a.tile_log2, dtype)
+        ref = oracle.apply_ops(H if dtype == "c128" else H.astype(np.complex64).astype(np.complex128), ops)
+        tol = 1e-12 if dtype == "c128" else (len(ops) + 1) * 2.0 ** -24 * 4
+        assert rel(a.to_dense(), ref) <= tol, (a.n, dtype, rel(a.to_dense(), ref))
+    batch.close()
+
+
+def test_autotune_rejects_an_empty_batch(ht):
+    b = ht.Batch()
+    with pytest.raises(ht.HermError):
+        b.autotune()
+    b.close()
