@@ -3,6 +3,7 @@
     python bench_ext.py batched   [--count 4096]
     python bench_ext.py serve     [--rates 10,100,1000] [--count 48]
     python bench_ext.py precision [--layers 4]
+    python bench_ext.py native    [--reps 5]
 
 Each prints one JSON line.  All inputs are seeded and synthetic (see synth/).
 
@@ -16,6 +17,9 @@ serve:     Poisson request streams (n log-uniform in 6..16, 10..300 mixed
            ops, c128/c64, half with a 64-term Pauli-sum readout) served by the
            continuous-batching server and by the one-at-a-time baseline on
            the same requests: circuits/s, p50/p99 latency, equal results.
+native:    permutation-and-phase gates (X, Z, T, dephasing, CNOT, CZ, SWAP,
+           Toffoli, CCZ, Fredkin) at n = 16 with the native pass and with
+           the generic pass: time per pass and algorithmic bytes moved.
 precision: the n = 16 layered workload in complex64 storage (FP64
            arithmetic and reductions) next to complex128: passes/s, and the
            complex64 error against the complex128 GPU state on sampled
@@ -234,6 +238,63 @@ def run_serve(args):
                                   "c128/c64 50/50; half with a 64-term Pauli-sum readout"}), flush=True)
 
 
+# ------------------------------------------------------------------- native
+
+def run_native(args):
+    """Permutation-and-phase gates at n = 16, c128, tile edge 32: each gate
+    at intra and tile-selecting positions, timed with the native pass and
+    with the generic pass (native off), on the same operator."""
+    import torch
+    import paper_2604_15765_amd as ht
+    import synth
+
+    torch.cuda.set_device(0)
+    n = 16
+    rng = synth.make_rng(args.seed)
+    h = ht.Herm(n, 5).init_lowrank(synth.ginibre_factor(n, 16, rng))
+    h.scale(1.0 / h.trace())
+    cases = [
+        ("X", [3], synth.named_gate("X")), ("X", [12], synth.named_gate("X")),
+        ("Z", [4], synth.named_gate("Z")), ("Z", [12], synth.named_gate("Z")),
+        ("T", [12], synth.named_gate("T")),
+        ("dephasing", [12], synth.dephasing_kraus(0.1)),
+        ("CNOT", [3, 4], synth.cnot_matrix()), ("CNOT", [8, 12], synth.cnot_matrix()),
+        ("CZ", [9, 13], synth.permutation_gate("CZ")), ("SWAP", [6, 11], synth.permutation_gate("SWAP")),
+        ("TOFFOLI", [3, 4, 12], synth.permutation_gate("TOFFOLI")),
+        ("TOFFOLI", [8, 10, 14], synth.permutation_gate("TOFFOLI")),
+        ("CCZ", [7, 9, 15], synth.permutation_gate("CCZ")),
+        ("FREDKIN", [5, 11, 13], synth.permutation_gate("FREDKIN")),
+    ]
+    results = []
+    for name, t, g in cases:
+        kraus = g if g.ndim == 3 else g[None]
+        row = {"gate": name, "targets": t}
+        for native in (1, 0):
+            if native == 0 and len(t) == 3:
+                continue  # k = 3 exists only in the native form
+            ht.set_tuning("native", native)
+            for _ in range(2):
+                h.apply_channel(t, kraus)
+            h.profile_reset()
+            h.profile_enable(True)
+            for _ in range(args.reps):
+                h.apply_channel(t, kraus)
+            prof = h.profile_read()
+            h.profile_enable(False)
+            (cls, v), = prof.items()
+            key = "native" if native else "generic"
+            row[key] = {"class": cls, "avg_ms": v["ms"] / v["launches"],
+                        "bytes_per_launch": v["bytes"] / v["launches"],
+                        "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+        ht.set_tuning("native", 1)
+        if "generic" in row:
+            row["speedup"] = row["generic"]["avg_ms"] / row["native"]["avg_ms"]
+        log(f"[native] {row}")
+        results.append(row)
+    print(json.dumps({"bench": "native", "n": n, "tile_edge": 32, "storage": "c128",
+                      "storage_bytes": h.nbytes, "results": results}), flush=True)
+
+
 # ---------------------------------------------------------------- precision
 
 def run_precision(args):
@@ -327,8 +388,12 @@ def main():
     r.add_argument("--layers", type=int, default=4)
     r.add_argument("--check-n", type=int, default=11, help="qubits of the oracle-checked run")
     r.add_argument("--seed", type=int, default=1616)
+    v = sub.add_parser("native")
+    v.add_argument("--seed", type=int, default=1616)
+    v.add_argument("--reps", type=int, default=5)
     args = p.parse_args()
-    {"batched": run_batched, "serve": run_serve, "precision": run_precision}[args.cmd](args)
+    {"batched": run_batched, "serve": run_serve, "precision": run_precision,
+     "native": run_native}[args.cmd](args)
 
 
 if __name__ == "__main__":

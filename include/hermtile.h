@@ -165,20 +165,33 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
 /* Apply a k-qubit unitary (or any 2^k x 2^k matrix) U by conjugation:
  * Schroedinger H -> U H U^dagger, Heisenberg H -> U^dagger H U
  * (Eq. (2) with one Kraus operator; Section II-A: unitaries keep the direct
- * two-sided block update).  k in {1, 2}; targets: k distinct qubits in
+ * two-sided block update).  k in {1, 2, 3}; targets: k distinct qubits in
  * [0, n); U: host, 2 * 4^k doubles, row-major, interleaved complex.  U is not
- * checked for unitarity.  Enqueued asynchronously; U is copied before return. */
+ * checked for unitarity.  Enqueued asynchronously; U is copied before return.
+ *
+ * Permutation-and-phase matrices (one nonzero per row: X, Y, Z, S, T, RZ,
+ * CNOT, CZ, SWAP, Toffoli, ... -- the gates of Section II-B) take a native
+ * pass that moves every changing entry once, with its phase, and does not
+ * touch the entries the gate fixes (a diagonal gate on a tile-selecting
+ * qubit touches half of the storage, a CNOT three quarters).  Fixed entries
+ * keep their bits; a phase product within 2^-50 of one on an entry the
+ * permutation fixes counts as one.  k = 3 is supported for such matrices
+ * only (HT_EUNSUPPORTED otherwise).  ht_set_tuning("native", 0) turns the
+ * native pass off (k <= 2 then takes the generic forms). */
 ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,
                            ht_picture picture);
 
 /* Apply the quantum operation with Kraus operators L_0..L_{r-1}:
  * Schroedinger H -> sum_a L_a H L_a^dagger (Eq. (1)), Heisenberg
- * H -> sum_a L_a^dagger H L_a.  k in {1, 2}; 1 <= r <= 4^k; kraus: host,
+ * H -> sum_a L_a^dagger H L_a.  k in {1, 2, 3}; 1 <= r <= 4^k; kraus: host,
  * r consecutive 2^k x 2^k row-major complex matrices (2 * r * 4^k doubles).
  * For r > 1 the map is applied through its transfer matrix (Eq. (3),
- * built on the host in FP64).  Trace-preservation is not required (the
- * algorithms hold for trace non-increasing maps, Section IV-A).  Enqueued
- * asynchronously; kraus is copied before return. */
+ * built on the host in FP64).  Kraus sets whose operators all have one
+ * nonzero per row in the same columns (dephasing, for example) take the
+ * native pass described at ht_apply_unitary; k = 3 only in that case.
+ * Trace-preservation is not required (the algorithms hold for trace
+ * non-increasing maps, Section IV-A).  Enqueued asynchronously; kraus is
+ * copied before return. */
 ht_status ht_apply_channel(ht_herm* h, int k, const int* targets, int r, const double* kraus,
                            ht_picture picture);
 
@@ -228,7 +241,9 @@ ht_status ht_batch_destroy(ht_batch* b);
 ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value);
 
 /* Queue one op for operator h; arguments as ht_apply_unitary /
- * ht_apply_channel.  The matrices are prepared and copied before return.
+ * ht_apply_channel, with k in {1, 2} and the generic forms only (the batch
+ * kernel has no native pass).  The matrices are prepared and copied before
+ * return.
  * h must stay alive until the run that executes the op has finished. */
 ht_status ht_batch_add_unitary(ht_batch* b, ht_herm* h, int k, const int* targets, const double* U,
                                ht_picture picture);
@@ -397,7 +412,9 @@ const char* ht_kernel_class_name(int idx);
  * nontemporal loads and stores when every store writes whole cache lines);
  * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
  * 0): 0 = each wave processes whole tile groups, 1 = the patches of a group
- * are spread over neighbouring waves.  HT_EINVAL for an unknown name or value. */
+ * are spread over neighbouring waves.  "native" (0 or 1, default 1): the
+ * native pass for permutation-and-phase operations.  HT_EINVAL for an
+ * unknown name or value. */
 ht_status ht_set_tuning(const char* name, int64_t value);
 
 /* Pure host function (no GPU): the per-op preparation the library performs
@@ -411,8 +428,12 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  *                      matrix A, applied as A h A^dagger), 1: transfer form
  *                      (coef holds the 4^k x 4^k matrix S acting on the
  *                      row-major vector of a block, S = sum_a A_a (x) conj(A_a)),
+ *                      2: native permutation-and-phase form (coef holds the
+ *                      2^k x 2^k coefficients c, then 2^k doubles p(0..2^k-1);
+ *                      block entry w[u][v] = c[u][v] h[p(u)][p(v)]),
  *   coef               interleaved complex, row-major: 2 * 4^k doubles for
- *                      form 0, 2 * 16^k doubles for form 1 (512 always suffice),
+ *                      form 0, 2 * 16^k for form 1, 2 * 4^k + 2^k for form 2
+ *                      (512 always suffice),
  * where the A_a are the caller's operators with their local bits reordered to
  * ascending target order and, in the Heisenberg picture, adjoined. */
 ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,

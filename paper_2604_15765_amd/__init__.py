@@ -163,17 +163,20 @@ def prepare_op(n: int, tile_log2: int, targets: Sequence[int], mats, picture: in
         mats = mats[None]
     k = len(targets)
     t = np.ascontiguousarray(targets, dtype=np.int32)
-    st = np.zeros(2, dtype=np.int32)
+    st = np.zeros(3, dtype=np.int32)
     nc = ctypes.c_int()
     form = ctypes.c_int()
     coef = np.zeros(2 * 256, dtype=np.float64)
     _check(lib.ht_prepare_op(n, tile_log2, k, _ptr(t), mats.shape[0], _ptr(mats), picture,
                              _ptr(st), ctypes.byref(nc), ctypes.byref(form), _ptr(coef)))
     d = 1 << k
-    ne = d * d if form.value == 0 else d ** 4
+    ne = d ** 4 if form.value == 1 else d * d
     c = coef[:2 * ne].view(np.complex128)
-    side = d if form.value == 0 else d * d
-    return list(st[:k]), nc.value, form.value, c.reshape(side, side).copy()
+    side = d * d if form.value == 1 else d
+    out = (list(st[:k]), nc.value, form.value, c.reshape(side, side).copy())
+    if form.value == 2:  # native form: also the permutation
+        return out + ([int(x) for x in coef[2 * ne:2 * ne + d]],)
+    return out
 
 
 class Herm:

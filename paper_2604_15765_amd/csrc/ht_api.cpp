@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -395,6 +396,12 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src) {
   return HT_OK;
 }
 
+// A k = 3 operation outside the native form is valid input the library does
+// not implement; every other preparation failure is an invalid argument.
+static ht_status op_error(const char* msg) {
+  return std::strncmp(msg, "k = 3 is supported", 18) == 0 ? HT_EUNSUPPORTED : HT_EINVAL;
+}
+
 static ht_status apply(ht_herm* h, int k, const int* targets, int r, const double* mats,
                        ht_picture picture) {
   if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
@@ -403,10 +410,15 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
   ht::PreparedOp op;
   char msg[256];
   if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
-                     sizeof msg) != 0)
-    return ht_fail(HT_EINVAL, "%s", msg);
+                     sizeof msg, ht::tuning().native) != 0)
+    return ht_fail(op_error(msg), "%s", msg);
   ht_device_guard dg(h->device);
   if (op.k == 2 && op.form == 1) HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 512, h->stream));
+  if (op.form == 2) {
+    double data[512];
+    const int nd = ht::native_op_data(op, data);
+    HT_HIP(ht::launch_upload(h->coef_dev, data, nd, h->stream));
+  }
   hipEvent_t a = nullptr, b = nullptr;
   if (h->prof) {
     a = take_event(h);
@@ -414,11 +426,18 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
     if (!a || !b) return ht_fail(HT_EDEVICE, "could not create profiling events");
     HT_HIP(hipEventRecord(a, h->stream));
   }
-  HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
+  if (op.form == 2)
+    HT_HIP(ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
+  else
+    HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
   if (h->prof) {
     HT_HIP(hipEventRecord(b, h->stream));
     const int cls = h->dtype * ht::kClassesPerDtype + ht::conj_class(op.k, op.ncross, op.form);
-    h->pending.push_back(ht_pending_event{cls, a, b, 2.0 * (double)h->bytes});
+    // algorithmic bytes: every stored entry read and written once, or for the
+    // native pass the changing fraction of them
+    double frac = 1.0;
+    if (op.form == 2) frac = (double)__builtin_popcountll(op.active) / (double)(1 << (2 * op.k));
+    h->pending.push_back(ht_pending_event{cls, a, b, 2.0 * frac * (double)h->bytes});
   }
   return HT_OK;
 }
@@ -538,14 +557,20 @@ ht_status ht_profile_read(ht_herm* h, int max_classes, int* nclasses, int64_t* l
 }
 
 const char* ht_kernel_class_name(int idx) {
-  static const char* names[2 * ht::kClassesPerDtype] = {
-      "c128_k1_c0_direct", "c128_k1_c0_transfer", "c128_k1_c1_direct", "c128_k1_c1_transfer",
-      "c128_k2_c0_direct", "c128_k2_c0_transfer", "c128_k2_c1_direct", "c128_k2_c1_transfer",
-      "c128_k2_c2_direct", "c128_k2_c2_transfer", "c64_k1_c0_direct",  "c64_k1_c0_transfer",
-      "c64_k1_c1_direct",  "c64_k1_c1_transfer",  "c64_k2_c0_direct",  "c64_k2_c0_transfer",
-      "c64_k2_c1_direct",  "c64_k2_c1_transfer",  "c64_k2_c2_direct",  "c64_k2_c2_transfer"};
+  static const char* names[ht::kClassesPerDtype] = {
+      "k1_c0_direct", "k1_c0_transfer", "k1_c1_direct", "k1_c1_transfer", "k2_c0_direct",
+      "k2_c0_transfer", "k2_c1_direct", "k2_c1_transfer", "k2_c2_direct", "k2_c2_transfer",
+      "k1_c0_native", "k1_c1_native", "k2_c0_native", "k2_c1_native", "k2_c2_native",
+      "k3_c0_native", "k3_c1_native", "k3_c2_native", "k3_c3_native"};
+  static std::string full[2 * ht::kClassesPerDtype];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int d = 0; d < 2; ++d)
+      for (int i = 0; i < ht::kClassesPerDtype; ++i)
+        full[d * ht::kClassesPerDtype + i] = std::string(d == 0 ? "c128_" : "c64_") + names[i];
+  });
   if (idx < 0 || idx >= 2 * ht::kClassesPerDtype) return nullptr;
-  return names[idx];
+  return full[idx].c_str();
 }
 
 ht_status ht_set_tuning(const char* name, int64_t value) {
@@ -567,6 +592,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().order = (int)value;
     return HT_OK;
   }
+  if (k == "native") {
+    if (value != 0 && value != 1) return ht_fail(HT_EINVAL, "native must be 0 or 1");
+    ht::tuning().native = (int)value;
+    return HT_OK;
+  }
   if (k == "conj_mem_mode") {
     if (value < -1 || value > 3) return ht_fail(HT_EINVAL, "conj_mem_mode must be in [-1, 3]");
     ht::tuning().mem_mode = (int)value;
@@ -584,16 +614,19 @@ ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
     return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   ht::PreparedOp op;
   char msg[256];
-  if (ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg, sizeof msg) != 0)
-    return ht_fail(HT_EINVAL, "%s", msg);
+  if (ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg, sizeof msg,
+                     ht::tuning().native) != 0)
+    return ht_fail(op_error(msg), "%s", msg);
   if (sorted_targets)
     for (int l = 0; l < op.k; ++l) sorted_targets[l] = op.sorted[l];
   if (ncross) *ncross = op.ncross;
   if (form) *form = op.form;
   if (coef) {
     const int D = 1 << op.k;
-    const int ne = op.form == 0 ? D * D : D * D * D * D;
+    const int ne = op.form == 1 ? D * D * D * D : D * D;
     std::memcpy(coef, op.coef, sizeof(double) * 2 * ne);
+    if (op.form == 2)
+      for (int u = 0; u < D; ++u) coef[2 * ne + u] = (double)op.perm[u];
   }
   return HT_OK;
 }

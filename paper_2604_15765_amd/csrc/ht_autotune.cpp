@@ -78,7 +78,7 @@ class Tuner {
       for (const auto& r : tr.e->raw) {
         ht::PreparedOp op;
         if (ht::prepare_op(n, m, r.k, r.targets, r.r, tr.e->mats.data() + r.mat_off, r.heisenberg,
-                           &op, msg, sizeof msg) != 0)
+                           &op, msg, sizeof msg, ht::tuning().native) != 0)
           return ht_fail(HT_EINVAL, "autotune: %s", msg);
         ht::append_batch_op(op, tr.ops, tr.coefs);
       }

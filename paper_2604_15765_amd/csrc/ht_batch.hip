@@ -13,6 +13,7 @@
 // XCD's L2 or the Infinity Cache between consecutive ops.
 #include "ht_geom.h"
 #include "ht_internal.h"
+#include "ht_native.h"
 
 namespace ht {
 
@@ -42,11 +43,37 @@ __device__ void batch_pass(S2<T>* base, int n, int m, const BatchOp& op,
   }
 }
 
+// Native permutation-and-phase pass of one op over one operator, one block
+// per lane at a time (the kernel's budget at 1024 threads is 128 VGPRs).
+template <typename T, int K, int C>
+__device__ void batch_native(S2<T>* base, int n, int m, const BatchOp& op,
+                             const double* __restrict__ coefs, uint32_t wave, uint32_t nwaves,
+                             uint32_t lane) {
+  const ConjGeom<K, C> g = make_geom<K, C>(n, m, op.sorted);
+  NativeOp<K> nop;
+#pragma unroll
+  for (int u = 0; u < (1 << K); ++u) nop.perm[u] = op.perm[u];
+  nop.active = op.active;
+  nop.nchunks = 0;  // k <= 2: whole blocks
+  nop.c = coefs + op.coef_off;
+  const DirectMem<T, 0> mem{base};
+  for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves)
+    native_group_lane<1, K, C>(mem, g, native_group<K, C>(grp, g), nop, lane);
+}
+
 template <typename T>
 __device__ void batch_dispatch(S2<T>* base, int n, int m, const BatchOp& op,
                                const double* __restrict__ coefs, uint32_t wave, uint32_t nwaves,
                                uint32_t lane) {
   const int k = op.k, c = op.ncross, f = op.form;
+  if (f == 2) {
+    if (k == 1 && c == 0) return batch_native<T, 1, 0>(base, n, m, op, coefs, wave, nwaves, lane);
+    if (k == 1 && c == 1) return batch_native<T, 1, 1>(base, n, m, op, coefs, wave, nwaves, lane);
+    if (k == 2 && c == 0) return batch_native<T, 2, 0>(base, n, m, op, coefs, wave, nwaves, lane);
+    if (k == 2 && c == 1) return batch_native<T, 2, 1>(base, n, m, op, coefs, wave, nwaves, lane);
+    if (k == 2 && c == 2) return batch_native<T, 2, 2>(base, n, m, op, coefs, wave, nwaves, lane);
+    return;
+  }
 #define HT_CASE(K_, C_, F_) \
   if (k == K_ && c == C_ && f == F_) return batch_pass<T, K_, C_, F_>(base, n, m, op, coefs, wave, nwaves, lane);
   HT_CASE(1, 0, 0)

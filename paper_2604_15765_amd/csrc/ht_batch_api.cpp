@@ -28,10 +28,11 @@ ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, cons
     return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   if (!b->entries.empty() && h->device != b->device)
     return ht_fail(HT_EINVAL, "all operators of a batch must live on one device");
+  if (k != 1 && k != 2) return ht_fail(HT_EINVAL, "batches take ops with k = 1 or 2");
   ht::PreparedOp op;
   char msg[256];
   if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
-                     sizeof msg) != 0)
+                     sizeof msg, ht::tuning().native) != 0)
     return ht_fail(HT_EINVAL, "%s", msg);
   auto it = b->index.find(h);
   size_t e;

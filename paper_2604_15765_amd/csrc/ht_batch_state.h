@@ -37,7 +37,7 @@ struct ht_batch {
 
 namespace ht {
 
-// Append a prepared op to an op list and its coefficients to coefs.
+// Append a prepared op (k <= 2) to an op list and its coefficients to coefs.
 inline void append_batch_op(const PreparedOp& op, std::vector<BatchOp>& ops,
                             std::vector<double>& coefs) {
   BatchOp bo{};
@@ -47,9 +47,9 @@ inline void append_batch_op(const PreparedOp& op, std::vector<BatchOp>& ops,
   bo.sorted[0] = op.sorted[0];
   bo.sorted[1] = op.k > 1 ? op.sorted[1] : 0;
   bo.coef_off = (uint32_t)coefs.size();
-  const int D = 1 << op.k;
-  const int nd = 2 * (op.form == 0 ? D * D : D * D * D * D);
-  coefs.insert(coefs.end(), op.coef, op.coef + nd);
+  for (int u = 0; u < 4; ++u) bo.perm[u] = u < (1 << op.k) ? op.perm[u] : u;
+  bo.active = (uint32_t)op.active;
+  coefs.insert(coefs.end(), op.coef, op.coef + op_coef_doubles(op.k, op.form));
   ops.push_back(bo);
 }
 

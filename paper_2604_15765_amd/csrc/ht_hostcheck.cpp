@@ -10,6 +10,8 @@
 #include <cstring>
 
 #include "ht_geom.h"
+#include "ht_internal.h"
+#include "ht_native.h"
 #include "ht_prep.h"
 
 namespace {
@@ -65,6 +67,33 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
   }
 }
 
+template <int K, int C>
+void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop,
+                uint64_t* lanes_run) {
+  const ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, pop.sorted);
+  ht::NativeOp<K> op;
+  for (int u = 0; u < (1 << K); ++u) op.perm[u] = pop.perm[u];
+  op.active = pop.active;
+  op.nchunks = pop.nchunks;
+  double data[512];
+  ht::native_op_data(pop, data);
+  op.c = data;
+  for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
+    const ht::NativeGroup ng = ht::native_group<K, C>(grp, g);
+    for (uint32_t lane = 0; lane < 64; ++lane) {
+      if constexpr (K == 3) {
+        if (pop.chunk == 32)
+          ht::native3_group_lane<C, 32>(mem, g, ng, op, lane);
+        else
+          ht::native3_group_lane<C, 16>(mem, g, ng, op, lane);
+      }
+      else
+        ht::native_group_lane<ht::native_unroll(K), K, C>(mem, g, ng, op, lane);
+      ++*lanes_run;
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -72,15 +101,19 @@ extern "C" {
 // raw: host c128 tiled storage of nelems entries (2*nelems doubles), updated
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
-// ranges of the flattened work order.  Returns 0 on success, 1 on invalid op, 2 on an
+// ranges of the flattened work order (generic passes).  native: allow the
+// native pass for permutation-and-phase operations; *form (if not NULL)
+// receives the form used.  Returns 0 on success, 1 on invalid op, 2 on an
 // out-of-range access.  *lanes_run receives the number of lane bodies run.
 int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, const int* targets,
                      int r, const double* kraus, int heisenberg, int32_t* write_counts,
-                     int32_t* read_counts, uint64_t* lanes_run, int order, char* err,
-                     size_t errlen) {
+                     int32_t* read_counts, uint64_t* lanes_run, int order, int native,
+                     int* form, char* err, size_t errlen) {
   const int m = tile_log2 < n ? tile_log2 : n;
   ht::PreparedOp op;
-  if (ht::prepare_op(n, m, k, targets, r, kraus, heisenberg, &op, err, errlen) != 0) return 1;
+  if (ht::prepare_op(n, m, k, targets, r, kraus, heisenberg, &op, err, errlen, native) != 0)
+    return 1;
+  if (form) *form = op.form;
   bool oob = false;
   CheckedMem mem{reinterpret_cast<double2*>(raw), nelems, write_counts, read_counts, &oob};
   uint64_t lanes = 0;
@@ -98,6 +131,18 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   HT_CASE(2, 2, 0)
   HT_CASE(2, 2, 1)
 #undef HT_CASE
+#define HT_NATIVE(K_, C_) \
+  if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, &lanes);
+  HT_NATIVE(1, 0)
+  HT_NATIVE(1, 1)
+  HT_NATIVE(2, 0)
+  HT_NATIVE(2, 1)
+  HT_NATIVE(2, 2)
+  HT_NATIVE(3, 0)
+  HT_NATIVE(3, 1)
+  HT_NATIVE(3, 2)
+  HT_NATIVE(3, 3)
+#undef HT_NATIVE
   if (lanes_run) *lanes_run = lanes;
   if (oob) {
     if (err && errlen) std::snprintf(err, errlen, "out-of-range access");

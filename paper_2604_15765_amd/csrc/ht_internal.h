@@ -10,16 +10,21 @@
 namespace ht {
 
 // Number of kernel classes per dtype: (k, c, form) with c <= k.
-constexpr int kClassesPerDtype = 10;
+constexpr int kClassesPerDtype = 19;
 // Class index of (k, c, form) within a dtype: k=1 -> c*2+form (0..3),
-// k=2 -> 4 + c*2 + form (4..9).
-inline int conj_class(int k, int c, int form) { return (k == 1 ? 0 : 4) + c * 2 + form; }
+// k=2 -> 4 + c*2 + form (4..9); native form (2): k=1 -> 10 + c,
+// k=2 -> 12 + c, k=3 -> 15 + c (10..18).
+inline int conj_class(int k, int c, int form) {
+  if (form == 2) return 10 + (k == 1 ? c : k == 2 ? 2 + c : 5 + c);
+  return (k == 1 ? 0 : 4) + c * 2 + form;
+}
 
 struct LaunchTuning {
   int block_threads = 256;  // 4 waves per workgroup
   int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
   int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
   int order = 0;            // 0: a wave walks a whole group; 1: waves share a group's patches
+  int native = 1;           // 1: permutation-and-phase operations use the native pass
 };
 LaunchTuning& tuning();
 
@@ -28,6 +33,20 @@ LaunchTuning& tuning();
 // coefficients from memory (two-qubit transfer form); the caller uploads it.
 hipError_t launch_conj(int dtype, void* buf, int n, int m, const PreparedOp& op,
                        const double* coef_dev, int num_cu, hipStream_t s);
+
+// Enqueue one native pass (op.form == 2); coef_dev holds what native_op_data
+// wrote (uploaded by the caller).
+hipError_t launch_native(int dtype, void* buf, int n, int m, const PreparedOp& op,
+                         const double* coef_dev, int num_cu, hipStream_t s);
+// Device data of a native op: the coefficients, then for k = 3 the chunk
+// schedule, one entry per double.  Returns the number of doubles (<= 512).
+inline int native_op_data(const PreparedOp& op, double* out) {
+  const int nc = 2 << (2 * op.k);
+  for (int i = 0; i < nc; ++i) out[i] = op.coef[i];
+  if (op.k != 3) return nc;
+  for (int i = 0; i < op.nchunks * op.chunk; ++i) out[nc + i] = (double)op.sched[i];
+  return nc + op.nchunks * op.chunk;
+}
 
 // Elementwise and reduction kernels over the tiled storage.
 hipError_t launch_fill_zero(void* buf, size_t bytes, hipStream_t s);
@@ -76,7 +95,14 @@ struct BatchOp {
   int32_t k, ncross, form;
   int32_t sorted[2];
   uint32_t coef_off;  // offset (in doubles) of its coefficients in the batch's array
+  int32_t perm[4];    // native form: source local index of local index u
+  uint32_t active;    // native form: bit u * 2^k + v set when entry (u, v) changes
 };
+// Number of doubles of coefficients an op of this shape carries.
+inline int op_coef_doubles(int k, int form) {
+  const int D = 1 << k;
+  return 2 * (form == 1 ? D * D * D * D : D * D);
+}
 // One operator of a batch: its storage, shape and op range.
 struct BatchOperator {
   void* buf;

@@ -10,24 +10,40 @@
 //     S = sum_a A_a (x) conj(A_a), the transfer matrix for a row-major block
 //     vector.  (Eq. (3) stacks columns and uses conj(L) (x) L; gathering rows,
 //     as the tile algorithms do, swaps the factors.)
+//  4. recognises permutation-and-phase operations (Section II-B: gates whose
+//     matrix has one nonzero per row, such as X, Z, S, T, CNOT, SWAP or
+//     Toffoli, and Kraus sets of such matrices sharing one permutation, such
+//     as dephasing): there every output entry is one input entry times a
+//     coefficient, w[u][v] = c[u][v] h[p(u)][p(v)] with
+//     c[u][v] = sum_a A_a[u][p(u)] conj(A_a[v][p(v)]), and entries with
+//     p(u) = u, p(v) = v and c[u][v] = 1 do not change at all, so the pass
+//     need not touch them.
 #include "ht_prep.h"
 
+#include <algorithm>
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 namespace ht {
 
 using cplx = std::complex<double>;
 
+// Coefficients within this distance of one, on entries the permutation fixes,
+// are taken as exactly one (|d|^2 of a unit phase such as exp(i pi / 4) is
+// one only up to rounding): the entry is then left untouched, an error of at
+// most 4 units in the last place instead of the product's own rounding.
+constexpr double kUnitSnap = 1.0 / 1125899906842624.0;  // 2^-50
+
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
-               int heisenberg, PreparedOp* out, char* err, size_t errlen) {
+               int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native) {
   auto fail = [&](const char* msg) {
     if (err && errlen) std::snprintf(err, errlen, "%s", msg);
     return 1;
   };
   if (!out) return fail("output pointer is NULL");
-  if (k != 1 && k != 2) return fail("k must be 1 or 2");
+  if (k < 1 || k > 3) return fail("k must be 1, 2 or 3");
   if (!targets) return fail("targets is NULL");
   if (!kraus) return fail("operator matrices pointer is NULL");
   const int D = 1 << k;
@@ -39,11 +55,13 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
   }
 
   // perm[ls] = user local bit that becomes sorted local bit ls
-  int perm[2] = {0, 1};
-  if (k == 2 && targets[1] < targets[0]) {
-    perm[0] = 1;
-    perm[1] = 0;
-  }
+  int perm[3] = {0, 1, 2};
+  for (int a = 1; a < k; ++a)
+    for (int b = a; b > 0 && targets[perm[b]] < targets[perm[b - 1]]; --b) {
+      const int t = perm[b];
+      perm[b] = perm[b - 1];
+      perm[b - 1] = t;
+    }
   for (int ls = 0; ls < k; ++ls) out->sorted[ls] = targets[perm[ls]];
   out->k = k;
   out->ncross = 0;
@@ -56,7 +74,7 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
     return u;
   };
 
-  cplx A[16][16];  // up to r = 16 operators of 4x4
+  static thread_local cplx A[64][64];  // up to r = 64 operators of 8 x 8
   for (int a = 0; a < r; ++a) {
     const double* L = kraus + (size_t)2 * D * D * a;
     for (int us = 0; us < D; ++us)
@@ -68,6 +86,91 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
         A[a][us * D + vs] = e;
       }
   }
+
+  // permutation-and-phase form: one nonzero per row, same column in every A_a
+  bool mono = allow_native != 0;
+  int pm[8];
+  for (int u = 0; u < D && mono; ++u) {
+    pm[u] = -1;
+    for (int a = 0; a < r && mono; ++a)
+      for (int v = 0; v < D; ++v) {
+        if (A[a][u * D + v] == cplx(0.0, 0.0)) continue;
+        if (pm[u] < 0 && a == 0)
+          pm[u] = v;
+        else if (pm[u] != v)
+          mono = false;
+      }
+    if (pm[u] < 0) mono = false;  // a zero row in the first operator
+  }
+  if (mono) {  // pm must be a permutation
+    int seen = 0;
+    for (int u = 0; u < D; ++u) seen |= 1 << pm[u];
+    mono = seen == (1 << D) - 1;
+  }
+  if (mono) {
+    out->form = 2;
+    out->active = 0;
+    for (int u = 0; u < D; ++u) out->perm[u] = pm[u];
+    for (int u = D; u < 8; ++u) out->perm[u] = u;
+    for (int u = 0; u < D; ++u)
+      for (int v = 0; v < D; ++v) {
+        cplx c = 0.0;
+        for (int a = 0; a < r; ++a) c += A[a][u * D + pm[u]] * std::conj(A[a][v * D + pm[v]]);
+        const bool fixed = pm[u] == u && pm[v] == v;
+        if (fixed && std::abs(c.real() - 1.0) <= kUnitSnap && std::abs(c.imag()) <= kUnitSnap)
+          c = 1.0;
+        if (!fixed || c != cplx(1.0, 0.0)) out->active |= (uint64_t)1 << (u * D + v);
+        out->coef[2 * (u * D + v)] = c.real();
+        out->coef[2 * (u * D + v) + 1] = c.imag();
+      }
+    // For k <= 2 the native pass pays off only when some entry stays in
+    // place (it then moves fewer bytes); an op that changes every entry (X,
+    // Y, ...) keeps the generic pass, which is exact for permutations too.
+    if (k <= 2 && out->active == (D * D == 64 ? ~(uint64_t)0 : (((uint64_t)1 << (D * D)) - 1)))
+      mono = false;
+  }
+  if (mono) {
+    // chunks of whole orbits (first fit, largest orbits first); a cycle of
+    // (u, v) -> (p(u), p(v)) is at most the lcm of two cycle lengths of p
+    // (<= 15), an orbit at most two cycles
+    out->nchunks = 0;
+    out->chunk = 16;
+    std::memset(out->sched, 0, sizeof out->sched);
+    if (k == 3) {
+      std::vector<std::vector<int>> orbits;
+      uint64_t seen = 0;
+      for (int e = 0; e < D * D; ++e) {
+        if (!((out->active >> e) & 1) || ((seen >> e) & 1)) continue;
+        std::vector<int> orb;
+        for (int start : {e, (e % D) * D + e / D})
+          for (int x = start; !((seen >> x) & 1); x = pm[x / D] * D + pm[x % D]) {
+            seen |= (uint64_t)1 << x;
+            orb.push_back(x);
+          }
+        if ((int)orb.size() > 16) out->chunk = 32;
+        orbits.push_back(orb);
+      }
+      std::stable_sort(orbits.begin(), orbits.end(),
+                       [](const std::vector<int>& a, const std::vector<int>& b) { return a.size() > b.size(); });
+      const int cap = 256 / out->chunk;
+      int fill[16] = {0};
+      for (const auto& orb : orbits) {
+        int ch = 0;
+        while (ch < out->nchunks && fill[ch] + (int)orb.size() > out->chunk) ++ch;
+        if (ch == cap) return fail("internal: native schedule does not fit");
+        if (ch == out->nchunks) ++out->nchunks;
+        for (int x : orb) {
+          const int u = x / D, v = x % D;
+          out->sched[ch * out->chunk + fill[ch]++] =
+              (uint16_t)(0x8000 | u | (v << 3) | (pm[u] << 6) | (pm[v] << 9));
+        }
+      }
+    }
+    return 0;
+  }
+  if (k == 3)
+    return fail("k = 3 is supported for permutation-and-phase operations only (one nonzero "
+                "per row of every Kraus operator, in the same column for all of them)");
 
   if (r == 1) {
     out->form = 0;

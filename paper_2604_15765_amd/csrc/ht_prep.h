@@ -2,21 +2,37 @@
 #pragma once
 
 #include <stddef.h>
+#include <stdint.h>
 
 namespace ht {
 
 struct PreparedOp {
-  int k;           // 1 or 2
-  int sorted[2];   // targets, ascending
+  int k;           // 1, 2 or 3
+  int sorted[3];   // targets, ascending
   int ncross;      // targets >= the effective tile exponent
-  int form;        // 0: direct (coef = A, 2^k x 2^k); 1: transfer (coef = S, 4^k x 4^k)
+  // 0: direct (coef = A, 2^k x 2^k); 1: transfer (coef = S, 4^k x 4^k);
+  // 2: native permutation-and-phase form (coef = c, 2^k x 2^k, with perm):
+  //    w[u][v] = c[u][v] * h[perm[u]][perm[v]]
+  int form;
+  int perm[8];         // form 2: source row/column of local index u
+  uint64_t active;     // form 2: bit u * 2^k + v set when entry (u, v) changes
+  // form 2, k = 3: the changing entries in chunks of `chunk` (16 or 32)
+  // entries, each chunk a union of whole orbits of (u, v) under
+  // (u, v) -> (perm[u], perm[v]) and (u, v) -> (v, u), so that a chunk can be
+  // updated in place once all its sources are loaded (the transpose joins
+  // the two entries that share storage in blocks on the diagonal).  Entry:
+  // bit 15 valid, bits 0-2 u, 3-5 v, 6-8 perm[u], 9-11 perm[v]; padding 0.
+  int nchunks, chunk;
+  uint16_t sched[256];
   double coef[2 * 256];
 };
 
 // Validate and prepare.  Returns 0 on success; otherwise writes a message to
 // err (errlen bytes) and returns nonzero.  m_eff is the effective tile
-// exponent of the operator (min(tile_log2, n)).
+// exponent of the operator (min(tile_log2, n)).  allow_native: use form 2
+// when every Kraus operator has one nonzero entry per row, in the same
+// column for all of them (k = 3 is accepted only in that form).
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
-               int heisenberg, PreparedOp* out, char* err, size_t errlen);
+               int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native = 1);
 
 }  // namespace ht

@@ -31,6 +31,7 @@
 #include "hermtile.h"
 #include "ht_batch_runner.h"
 #include "ht_handle.h"
+#include "ht_batch_state.h"
 #include "ht_internal.h"
 #include "ht_prep.h"
 
@@ -193,15 +194,17 @@ hipError_t enqueue_chunk(ht_server* s, Req* r, Slot& sl, size_t count) {
     op.form = b.form;
     op.sorted[0] = b.sorted[0];
     op.sorted[1] = b.sorted[1];
-    const int D = 1 << b.k;
-    const int nd = 2 * (b.form == 0 ? D * D : D * D * D * D);
+    for (int u = 0; u < 4; ++u) op.perm[u] = b.perm[u];
+    op.active = b.active;
+    const int nd = ht::op_coef_doubles(b.k, b.form);
     std::memcpy(op.coef, r->coefs.data() + b.coef_off, nd * sizeof(double));
-    if (op.k == 2 && op.form == 1 &&
-        (e = ht::launch_upload(sl.coef_dev, op.coef, 512, sl.stream)) != hipSuccess)
+    if (((op.k == 2 && op.form == 1) || op.form == 2) &&
+        (e = ht::launch_upload(sl.coef_dev, op.coef, op.form == 2 ? nd : 512, sl.stream)) != hipSuccess)
       return e;
-    if ((e = ht::launch_conj(r->dtype, r->buf, r->n, r->m, op, sl.coef_dev, s->num_cu, sl.stream)) !=
-        hipSuccess)
-      return e;
+    e = op.form == 2
+            ? ht::launch_native(r->dtype, r->buf, r->n, r->m, op, sl.coef_dev, s->num_cu, sl.stream)
+            : ht::launch_conj(r->dtype, r->buf, r->n, r->m, op, sl.coef_dev, s->num_cu, sl.stream);
+    if (e != hipSuccess) return e;
   }
   if ((e = hipEventRecord(sl.ev_chunk[r->chunk_ev], sl.stream)) != hipSuccess) return e;
   r->chunk_ev ^= 1;
@@ -523,22 +526,14 @@ ht_status ht_server_submit(ht_server* s, const ht_request* q, int64_t* id) {
   size_t mat_off = 0;
   for (int i = 0; i < q->nops; ++i) {
     const int k = q->op_k[i];
+    if (k != 1 && k != 2) return ht_fail(HT_EINVAL, "op %d: k must be 1 or 2 in a request", i);
     ht::PreparedOp op;
     char msg[256];
     if (ht::prepare_op(r->n, r->m, k, q->op_targets + 2 * i, q->op_r[i], q->op_mats + mat_off,
-                       q->picture == HT_HEISENBERG, &op, msg, sizeof msg) != 0)
+                       q->picture == HT_HEISENBERG, &op, msg, sizeof msg, ht::tuning().native) != 0)
       return ht_fail(HT_EINVAL, "op %d: %s", i, msg);
     mat_off += (size_t)2 * q->op_r[i] * (1u << (2 * k));
-    ht::BatchOp b{};
-    b.k = op.k;
-    b.ncross = op.ncross;
-    b.form = op.form;
-    b.sorted[0] = op.sorted[0];
-    b.sorted[1] = op.k > 1 ? op.sorted[1] : 0;
-    b.coef_off = (uint32_t)r->coefs.size();
-    const int D = 1 << k;
-    r->coefs.insert(r->coefs.end(), op.coef, op.coef + 2 * (op.form == 0 ? D * D : D * D * D * D));
-    r->ops.push_back(b);
+    ht::append_batch_op(op, r->ops, r->coefs);
   }
   for (int t = 0; t < q->nterms; ++t) {
     uint32_t x = 0, z = 0;

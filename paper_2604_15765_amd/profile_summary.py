@@ -45,12 +45,17 @@ def _csv(d, suffix):
 
 
 def kernel_class(name: str):
-    """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct'; None otherwise."""
+    """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct',
+    'native_kernel<float, 3, 2, 0>' -> 'c64_k3_c2_native'; None otherwise."""
     m = re.search(r"conj_kernel<(double|float), (\d), (\d), (\d), (\d)>", name)
-    if not m:
-        return None
-    dt = "c128" if m.group(1) == "double" else "c64"
-    return f"{dt}_k{m.group(2)}_c{m.group(3)}_{'direct' if m.group(4) == '0' else 'transfer'}"
+    if m:
+        dt = "c128" if m.group(1) == "double" else "c64"
+        return f"{dt}_k{m.group(2)}_c{m.group(3)}_{'direct' if m.group(4) == '0' else 'transfer'}"
+    m = re.search(r"native_kernel<(double|float), (\d), (\d), (\d)>", name)
+    if m:
+        dt = "c128" if m.group(1) == "double" else "c64"
+        return f"{dt}_k{m.group(2)}_c{m.group(3)}_native"
+    return None
 
 
 def _counter_avg(rows, counter, select):
@@ -129,7 +134,7 @@ def read_traffic(path: str):
     out = {}
     for line in text.splitlines():
         parts = line.split()
-        if len(parts) == 5 and re.match(r"c(128|64)_k\d_c\d_(direct|transfer)$", parts[0]):
+        if len(parts) == 5 and re.match(r"c(128|64)_k\d_c\d_(direct|transfer|native)$", parts[0]):
             out[parts[0]] = float(parts[4]) * 1e9
     return out
 

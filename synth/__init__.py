@@ -31,6 +31,8 @@ from .random_ops import (
     dephasing_kraus,
     named_gate,
     cnot_matrix,
+    permutation_gate,
+    random_monomial,
     random_pauli_sum,
     random_kraus_set,
 )
@@ -56,6 +58,8 @@ __all__ = [
     "dephasing_kraus",
     "named_gate",
     "cnot_matrix",
+    "permutation_gate",
+    "random_monomial",
     "random_pauli_sum",
     "random_kraus_set",
     "circuit_plain_n8",

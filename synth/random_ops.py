@@ -140,6 +140,47 @@ def cnot_matrix() -> np.ndarray:
     return m
 
 
+def permutation_gate(name: str) -> np.ndarray:
+    """Multi-qubit gates with one nonzero per row.  Local bit l belongs to
+    targets[l]: CZ (phase -1 on |11>), SWAP, ISWAP (swap with phase i),
+    TOFFOLI (bits 0, 1 control, bit 2 flips), CCZ (phase -1 on |111>),
+    FREDKIN (bit 0 controls a swap of bits 1 and 2)."""
+    name = name.upper()
+    if name in ("CZ", "SWAP", "ISWAP"):
+        d = 4
+    elif name in ("TOFFOLI", "CCZ", "FREDKIN"):
+        d = 8
+    else:
+        raise ValueError(f"unknown gate {name}")
+    m = np.zeros((d, d), dtype=np.complex128)
+    for u in range(d):
+        b = [(u >> l) & 1 for l in range(3)]
+        if name == "CZ":
+            m[u, u] = -1.0 if u == 3 else 1.0
+        elif name == "SWAP":
+            m[(u & ~3) | (b[0] << 1) | b[1], u] = 1.0
+        elif name == "ISWAP":
+            m[(b[0] << 1) | b[1], u] = 1j if b[0] != b[1] else 1.0
+        elif name == "TOFFOLI":
+            m[u ^ 4 if (b[0] and b[1]) else u, u] = 1.0
+        elif name == "CCZ":
+            m[u, u] = -1.0 if u == 7 else 1.0
+        else:  # FREDKIN
+            v = (b[0] | (b[2] << 1) | (b[1] << 2)) if b[0] else u
+            m[v, u] = 1.0
+    return m
+
+
+def random_monomial(k: int, rng: np.random.Generator, diagonal: bool = False) -> np.ndarray:
+    """A 2^k x 2^k unitary with one nonzero per row: a uniformly random
+    permutation (the identity when ``diagonal``) with uniform random phases."""
+    d = 1 << k
+    perm = np.arange(d) if diagonal else rng.permutation(d)
+    m = np.zeros((d, d), dtype=np.complex128)
+    m[np.arange(d), perm] = np.exp(2j * np.pi * rng.random(d))
+    return m
+
+
 def random_pauli_sum(n: int, nterms: int, rng: np.random.Generator):
     """``nterms`` Pauli strings uniform over {I,X,Y,Z}^n without the identity
     string, with N(0,1) real coefficients.  Returns (codes uint8 (nterms, n),

@@ -100,15 +100,71 @@ def test_prepare_op_reproduces_the_oracle(ht, picture):
 def test_prepare_op_rejects_bad_arguments(ht):
     U = np.eye(2)
     for bad in (dict(targets=[4]), dict(targets=[-1]), dict(targets=[1, 1], mats=np.eye(4)),
-                dict(targets=[0, 1, 2], mats=np.eye(8))):
+                dict(targets=[0, 1, 2, 3], mats=np.eye(16))):
         t = bad.get("targets")
         with pytest.raises(ht.HermError) as ei:
             ht.prepare_op(4, 2, t, bad.get("mats", U))
         assert ei.value.status == 1
+    # k = 3 exists only in the permutation-and-phase form
+    with pytest.raises(ht.HermError) as ei:
+        ht.prepare_op(4, 2, [0, 1, 2], synth.haar_unitary(8, synth.make_rng(3)))
+    assert ei.value.status == 4
     with pytest.raises(ht.HermError):
         ht.prepare_op(4, 2, [0], np.stack([np.eye(2)] * 5))  # r > 4^k
     with pytest.raises(ht.HermError):
         ht.prepare_op(4, 2, [0], U, picture=7)
+
+
+@pytest.mark.parametrize("picture", [0, 1])
+def test_prepare_op_native_form_reproduces_the_oracle(ht, picture):
+    """Permutation-and-phase ops prepare to form 2: coefficients c and a
+    permutation p with block entry w[u][v] = c[u][v] h[p(u)][p(v)] in
+    ascending target order; applied to every block this must reproduce the
+    oracle, and p must be the column of the single nonzero in each row of
+    the renumbered (and, for Heisenberg, adjoined) matrix."""
+    rng = synth.make_rng(17)
+    n = 4
+    H = synth.random_hermitian_dense(n, rng)
+    cases = [([1], synth.named_gate("S")[None]), ([3], synth.named_gate("T")[None]),
+             ([2], synth.dephasing_kraus(0.3)), ([3, 0], synth.cnot_matrix()[None]),
+             ([1, 2], synth.permutation_gate("ISWAP")[None]), ([0, 3], synth.random_monomial(2, rng, diagonal=True)[None]),
+             ([3, 1, 0], synth.permutation_gate("TOFFOLI")[None]), ([2, 0, 3], synth.random_monomial(3, rng)[None]),
+             ([1, 2, 3], np.kron(synth.named_gate("X"), np.kron(synth.named_gate("Y"), synth.named_gate("X")))[None])]
+    for targets, kraus in cases:
+        st, ncross, form, coef, perm = ht.prepare_op(n, 2, targets, kraus, picture)
+        assert form == 2 and st == sorted(targets)
+        k = len(targets)
+        order = np.argsort(targets)
+        user = [sum(((us >> ls) & 1) << int(order[ls]) for ls in range(k)) for us in range(1 << k)]
+        A0 = kraus[0][np.ix_(user, user)]
+        if picture:
+            A0 = A0.conj().T
+        assert perm == [int(np.flatnonzero(A0[u])[0]) for u in range(1 << k)]
+        ref = (oracle.kraus_map_adjoint if picture else oracle.kraus_map)(H, kraus, targets)
+        d = 1 << k
+        for s_ in range(1 << (n - k)):
+            for s2 in range(1 << (n - k)):
+                r = [oracle.insert_bits(s_, a, st) for a in range(d)]
+                c = [oracle.insert_bits(s2, a, st) for a in range(d)]
+                h = H[np.ix_(r, c)]
+                w = coef * h[np.ix_(perm, perm)]
+                assert np.allclose(w, ref[np.ix_(r, c)], atol=1e-13)
+
+
+def test_native_tuning_switch(ht):
+    try:
+        ht.set_tuning("native", 0)
+        assert ht.prepare_op(4, 2, [1], synth.named_gate("Z"))[2] == 0
+        with pytest.raises(ht.HermError):  # k = 3 has no generic form
+            ht.prepare_op(4, 2, [0, 1, 2], synth.permutation_gate("TOFFOLI"))
+    finally:
+        ht.set_tuning("native", 1)
+    assert ht.prepare_op(4, 2, [1], synth.named_gate("Z"))[2] == 2
+    # an op that changes every entry (k <= 2) gains nothing: generic form
+    assert ht.prepare_op(4, 2, [1], synth.named_gate("X"))[2] == 0
+    assert ht.prepare_op(4, 2, [1], synth.depolarising_kraus(0.1))[2] == 1
+    with pytest.raises(ht.HermError):
+        ht.set_tuning("native", 2)
 
 
 def test_tuning_validation(ht):
@@ -121,7 +177,8 @@ def test_tuning_validation(ht):
 
 def test_kernel_class_names(ht):
     names = ht.kernel_class_names()
-    assert len(names) == 20 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k2_c2_transfer"
+    assert len(names) == 38 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k3_c3_native"
+    assert names[10] == "c128_k1_c0_native" and names[19] == "c64_k1_c0_direct"
 
 
 def _c_layout(struct, fields, tmp_path):

@@ -19,6 +19,7 @@ import pytest
 
 import oracle
 import synth
+from tests.native_masks import changing_entries, expected_writes
 from oracle import layout
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,22 +34,27 @@ def hc():
     f = lib.htc_emulate_conj
     vp = ctypes.c_void_p
     f.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp,
-                  ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_char_p,
-                  ctypes.c_size_t]
+                  ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_int,
+                  ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, ctypes.c_size_t]
     f.restype = ctypes.c_int
     return f
 
 
-def emulate(f, raw, n, m, targets, kraus, heis, order=0):
+def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=False):
+    """Run one pass on the CPU.  native=0 keeps the generic forms (direct,
+    transfer); native=1 lets permutation-and-phase ops take the native pass."""
     raw = np.ascontiguousarray(raw, dtype=np.complex128).copy()
     kraus = np.ascontiguousarray(kraus, dtype=np.complex128)
     t = np.ascontiguousarray(targets, dtype=np.int32)
     wc = np.zeros(raw.size, dtype=np.int32)
     lanes = ctypes.c_uint64()
+    form = ctypes.c_int(-1)
     err = ctypes.create_string_buffer(256)
     rc = f(raw.ctypes.data, raw.size, n, m, len(targets), t.ctypes.data, kraus.shape[0], kraus.ctypes.data,
-           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, err, 256)
+           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, native, ctypes.byref(form), err, 256)
     assert rc == 0, err.value.decode()
+    if want_form:
+        return raw, wc, form.value
     return raw, wc
 
 
@@ -126,13 +132,110 @@ def test_diagonal_tile_halves_consistent_after_cross_op(hc):
         assert layout.diagonal_tile_asymmetry(raw, n, m) < 1e-14
 
 
-def test_pauli_x_twice_is_bitwise_identity(hc):
+@pytest.mark.parametrize("native", [0, 1])
+def test_pauli_x_twice_is_bitwise_identity(hc, native):
     rng = synth.make_rng(600)
     n, m = 6, 3
     H = synth.random_hermitian_dense(n, rng)
     raw = layout.encode(H, m)
     X = synth.named_gate("X")[None]
     for a in range(n):
-        once, _ = emulate(hc, raw, n, m, [a], X, False)
-        twice, _ = emulate(hc, once, n, m, [a], X, False)
+        once, _ = emulate(hc, raw, n, m, [a], X, False, native=native)
+        twice, _ = emulate(hc, once, n, m, [a], X, False, native=native)
         assert np.array_equal(twice, raw)
+
+
+# ------------------------------------------------------ native pass (form 2)
+
+def check_native(f, n, m, targets, kraus, heis, rng):
+    """Native pass: form 2 unless k <= 2 and every entry changes (then the
+    generic pass, which moves the same bytes); exactly the changing entries
+    are written, once each."""
+    H = synth.random_hermitian_dense(n, rng)
+    raw = layout.encode(H, m)
+    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, native=1, want_form=True)
+    changing = changing_entries(kraus, targets, heis)
+    assert form == (2 if len(targets) == 3 or not changing.all() else (0 if kraus.shape[0] == 1 else 1)), \
+        (targets, form)
+    expect = expected_writes(n, m, targets, changing)
+    assert np.array_equal(wc, expect), (n, m, targets, np.unique(wc - expect))
+    ref = reference(H, kraus, targets, heis)
+    e = rel(layout.decode(out, n, m), ref)
+    assert e < 1e-13, (n, m, targets, heis, e)
+    # untouched entries keep their bits; the rest agree with the generic pass
+    assert np.array_equal(out[expect == 0], raw[expect == 0])
+    if len(targets) < 3:
+        gen, _ = emulate(f, raw, n, m, targets, kraus, heis, native=0)
+        assert rel(layout.decode(gen, n, m), layout.decode(out, n, m)) < 1e-14
+
+
+NAMED_1Q = ["X", "Y", "Z", "S", "T"]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_native_single_qubit_gates_every_position(hc, m):
+    rng = synth.make_rng(700 + m)
+    gates = [synth.named_gate(g)[None] for g in NAMED_1Q]
+    gates.append(synth.named_gate("RZ", 0.37)[None])
+    gates.append(synth.dephasing_kraus(0.2))                 # diagonal Kraus set
+    X, Y = synth.named_gate("X"), synth.named_gate("Y")
+    gates.append(np.stack([np.sqrt(0.3) * X, np.sqrt(0.7) * (X @ synth.named_gate("S"))]))  # shared permutation
+    for n in range(1, 7):
+        for a in range(n):
+            for g in gates:
+                check_native(hc, n, m, [a], g, bool(rng.integers(2)), rng)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_native_two_qubit_gates_every_ordered_pair(hc, m):
+    rng = synth.make_rng(800 + m)
+    gates = [synth.cnot_matrix()[None]] + [synth.permutation_gate(g)[None] for g in ("CZ", "SWAP", "ISWAP")]
+    for n in range(2, 7):
+        for a, b in itertools.permutations(range(n), 2):
+            for g in gates:
+                check_native(hc, n, m, [a, b], g, bool(rng.integers(2)), rng)
+            check_native(hc, n, m, [a, b], synth.random_monomial(2, rng)[None], bool(rng.integers(2)), rng)
+            check_native(hc, n, m, [a, b], synth.random_monomial(2, rng, diagonal=True)[None], False, rng)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_native_three_qubit_gates(hc, m):
+    """k = 3 (Toffoli, CCZ, Fredkin, random permutation-and-phase matrices,
+    including permutations that are not involutions) on every ordered
+    triple at n = 3..5 and a sample at n = 6, every count of tile-selecting
+    targets."""
+    rng = synth.make_rng(900 + m)
+    gates = [synth.permutation_gate(g)[None] for g in ("TOFFOLI", "CCZ", "FREDKIN")]
+    for n in range(3, 7):
+        triples = list(itertools.permutations(range(n), 3))
+        if n == 6:
+            triples = [triples[i] for i in rng.choice(len(triples), 30, replace=False)]
+        for t in triples:
+            for g in gates:
+                check_native(hc, n, m, list(t), g, bool(rng.integers(2)), rng)
+            check_native(hc, n, m, list(t), synth.random_monomial(3, rng)[None], bool(rng.integers(2)), rng)
+
+
+def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
+    rng = synth.make_rng(950)
+    n, m = 4, 2
+    raw = layout.encode(synth.random_hermitian_dense(n, rng), m)
+    cases = [([1], synth.named_gate("H")[None]), ([0], synth.haar_unitary(2, rng)[None]),
+             ([2], synth.amplitude_damping_kraus(0.1)), ([3], synth.depolarising_kraus(0.1)),
+             ([0, 3], synth.haar_unitary(4, rng)[None])]
+    for t, g in cases:
+        _, _, form = emulate(hc, raw, n, m, t, g, False, native=1, want_form=True)
+        assert form in (0, 1), (t, form)
+
+
+def test_three_qubit_ops_need_the_native_form(hc):
+    rng = synth.make_rng(960)
+    n, m = 4, 2
+    raw = np.ascontiguousarray(layout.encode(synth.random_hermitian_dense(n, rng), m))
+    kraus = np.ascontiguousarray(synth.haar_unitary(8, rng)[None])
+    t = np.array([0, 1, 3], dtype=np.int32)
+    err = ctypes.create_string_buffer(256)
+    lanes = ctypes.c_uint64()
+    rc = hc(raw.ctypes.data, raw.size, n, m, 3, t.ctypes.data, 1, kraus.ctypes.data, 0, None, None,
+            ctypes.byref(lanes), 0, 1, None, err, 256)
+    assert rc == 1 and b"k = 3" in err.value
