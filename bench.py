@@ -13,7 +13,10 @@ Output: one JSON line (rank 0).  ``value`` = conjugation passes per second
 over the K timed steps; ``roofline`` = algorithmic bytes (every stored entry
 read and written once per pass) / measured time of the kernel class that takes
 the most time, against MI355X's 8 TB/s; ``cpu_baseline`` = the CPU oracle
-(Eq. (2) block form, numpy) on a bounded sample, see ``cpu_baseline()``.
+(Eq. (2) block form, numpy) on a bounded sample, see ``cpu_baseline()``;
+``fused`` = the same steps from the same state with each layer run as a
+fused circuit (ops grouped into 2-qubit passes), see ``fused_run()``.
+``value`` is the op-by-op figure: one pass per op, as the method defines.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16] [--tile-log2 5]
 """
@@ -42,6 +45,7 @@ def parse():
     p.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     p.add_argument("--seed", type=int, default=1616)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fused", action="store_true", help="skip the fused-circuit run of the same steps")
     p.add_argument("--cpu-sample-n", type=int, default=12,
                    help="qubits of the dense sub-operator the CPU oracle is timed on")
     p.add_argument("--tune", action="append", default=[], metavar="NAME=VALUE",
@@ -60,7 +64,7 @@ def cpu_baseline(n_full: int, n_sample: int, seed: int) -> dict:
     """Time the CPU oracle on a bounded sample of the workload.
 
     Sample: the 2^s x 2^s sub-operator (s = n_sample) that fixing the top
-    n_full - s qubits selects, evolved by one layer of the same op mix on its s
+    n_full - s qubits selects, evolved by two layers of the same op mix on its s
     qubits (a k-local op on those qubits maps that sub-operator to itself), with
     the oracle's Eq. (2) block form over the dense matrix.  The oracle's cost is
     proportional to the number of entries, so the per-op time is scaled by
@@ -75,7 +79,7 @@ def cpu_baseline(n_full: int, n_sample: int, seed: int) -> dict:
     rng = synth.make_rng(seed)
     G = synth.ginibre_factor(n_sample, 16, rng)
     rho = oracle.density_from_factor(G)
-    ops = synth.layer_n16(0, rng, n=n_sample)
+    ops = synth.layer_n16(0, rng, n=n_sample) + synth.layer_n16(1, rng, n=n_sample)
     t0 = time.perf_counter()
     done = 0
     for op in ops:
@@ -93,9 +97,55 @@ def cpu_baseline(n_full: int, n_sample: int, seed: int) -> dict:
         "kind": "oracle",
         "sample": (f"oracle Eq.(2) block form (numpy complex128) on the {1 << n_sample}x{1 << n_sample} "
                    f"sub-operator of the n={n_full} state with the top {n_full - n_sample} qubits fixed, "
-                   f"{done} ops of one layer of the same mix on its {n_sample} qubits in {dt:.1f} s; "
+                   f"{done} ops of two layers of the same mix on its {n_sample} qubits in {dt:.1f} s; "
                    f"per-op time scaled by 4^{n_full - n_sample} to n={n_full}"),
         "seconds": dt,
+    }
+
+
+def fused_run(ht, h, G, layers, args, codes, coeffs, tr_plain, ev_plain) -> dict:
+    """The same steps from the same initial state with each layer applied as
+    a fused circuit (neighbouring ops composed on the host into 2-qubit
+    passes; planning and composition inside the timed region).  Reports its
+    throughput in the same unit and how far its readouts are from the
+    op-by-op run's."""
+    import torch
+    h.init_lowrank(G)
+    h.scale(1.0 / h.trace())
+    circuits = []
+
+    def step(ops):
+        c = ht.Circuit(ops)
+        npass = c.plan(ht.SCHRODINGER, 2)
+        c.apply(h)
+        circuits.append(c)
+        return npass, h.trace(), h.expectation_pauli_sum(codes, coeffs)
+
+    for l in range(args.warmup):
+        step(layers[l])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nops = npasses = 0
+    tr = ev = None
+    for l in range(args.warmup, args.warmup + args.steps):
+        npass, tr, ev = step(layers[l])
+        nops += len(layers[l])
+        npasses += npass
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] fused: {nops / elapsed:.1f} gate-conj/s, {npasses / args.steps:.1f} passes per step")
+    for c in circuits:
+        c.close()
+    return {
+        "value": nops / elapsed,
+        "unit": "gate-conj/s",
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "passes_per_step": npasses / args.steps,
+        "ops_per_step": nops / args.steps,
+        "trace_diff_vs_op_by_op": abs(tr - tr_plain),
+        "pauli_expectation_diff_vs_op_by_op": abs(ev - ev_plain),
+        "note": "each layer as one ht_circuit: neighbouring ops composed in FP64 into passes on at most "
+                "2 qubits (ops on disjoint qubits reordered), one streaming pass per group",
     }
 
 
@@ -225,6 +275,8 @@ def main():
         "final_trace": tr,
         "final_pauli_expectation": ev,
     }
+    if not args.no_fused:
+        out["fused"] = fused_run(ht, h, G, layers, args, codes, coeffs, tr, ev)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, min(args.cpu_sample_n, n), args.seed)

@@ -289,6 +289,46 @@ typedef struct {
 } ht_batch_tuning;
 ht_status ht_batch_autotune(ht_batch* b, int sample_operators, ht_batch_tuning* out);
 
+/* ------------------------------------------------------------ circuits -- */
+
+/* A circuit: an op sequence applied with fusion.  Every conjugation pass
+ * streams the whole operator (Section III-C), so neighbouring ops that
+ * together act on at most max_qubits qubits are composed on the host in FP64
+ * into one map (unitaries multiply; channels compose through their transfer
+ * matrices, Eq. (3)) and applied in one pass.  The planner takes the
+ * earliest op not yet applied and absorbs later ops that keep the group
+ * within max_qubits (growing towards the qubits of the next op that couples
+ * the group to other qubits), skipping past ops it cannot absorb as long as
+ * no skipped op shares a qubit with an absorbed one (ops on disjoint qubits
+ * commute).  A group of one op runs exactly as ht_apply_* runs it.  The
+ * result equals applying the ops one by one up to rounding.  Not
+ * thread-safe. */
+typedef struct ht_circuit ht_circuit;
+ht_status ht_circuit_create(ht_circuit** out);
+ht_status ht_circuit_destroy(ht_circuit* c); /* accepts NULL */
+/* Append an op (arguments as ht_apply_unitary / ht_apply_channel; k <= 3;
+ * targets in [0, HT_MAX_QUBITS), checked against n when applied).  The
+ * matrices are copied. */
+ht_status ht_circuit_add_unitary(ht_circuit* c, int k, const int* targets, const double* U);
+ht_status ht_circuit_add_channel(ht_circuit* c, int k, const int* targets, int r,
+                                 const double* kraus);
+ht_status ht_circuit_size(const ht_circuit* c, int64_t* nops);
+/* Group the ops into passes for picture (Heisenberg: the adjoint maps in
+ * reverse order) with at most max_qubits (0: no fusion, 1 or 2) qubits per
+ * pass; *npasses (may be NULL) receives the number of passes.  Pure host
+ * computation. */
+ht_status ht_circuit_plan(ht_circuit* c, ht_picture picture, int max_qubits, int64_t* npasses);
+/* Pass i of the last plan: *k qubits targets[0..k) (ascending), *nops ops
+ * with their indices in the circuit as added (op_indices, nops entries, in
+ * the order they are composed), and its transfer matrix (transfer: 2 * 16^k
+ * doubles, row-major on the row-major block vector with local bit l at
+ * targets[l]; k <= 2).  Any output may be NULL. */
+ht_status ht_circuit_pass_info(const ht_circuit* c, int64_t i, int* k, int* targets, int64_t* nops,
+                               int64_t* op_indices, double* transfer);
+/* Enqueue the passes of the last plan on h's stream.  Every pass is prepared
+ * before any is enqueued: on an error (a target >= n, ...) h is untouched. */
+ht_status ht_circuit_apply(ht_circuit* c, ht_herm* h);
+
 /* --------------------------------------------------------------- graphs -- */
 
 /* Capture hot-path calls into a HIP graph and replay them with one launch.

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch  # first: the library must bind to the HIP runtime torch has loaded
 
-__all__ = ["Herm", "Batch", "Graph", "Server", "capture_begin", "capture_end", "lib", "SCHRODINGER",
+__all__ = ["Herm", "Batch", "Circuit", "Graph", "Server", "capture_begin", "capture_end", "lib", "SCHRODINGER",
            "HEISENBERG", "HermError", "storage_bytes", "effective_tile_log2", "prepare_op",
            "kernel_class_names", "set_tuning"]
 
@@ -97,6 +97,14 @@ def _load():
         "ht_batch_run": (c_int, [vp, vp]),
         "ht_batch_clear": (c_int, [vp]),
         "ht_batch_autotune": (c_int, [vp, c_int, vp]),
+        "ht_circuit_create": (c_int, [P(vp)]),
+        "ht_circuit_destroy": (c_int, [vp]),
+        "ht_circuit_add_unitary": (c_int, [vp, c_int, vp, vp]),
+        "ht_circuit_add_channel": (c_int, [vp, c_int, vp, c_int, vp]),
+        "ht_circuit_size": (c_int, [vp, P(c_int64)]),
+        "ht_circuit_plan": (c_int, [vp, c_int, c_int, P(c_int64)]),
+        "ht_circuit_pass_info": (c_int, [vp, c_int64, P(c_int), vp, P(c_int64), vp, vp]),
+        "ht_circuit_apply": (c_int, [vp, vp]),
         "ht_capture_begin": (c_int, [vp]),
         "ht_capture_end": (c_int, [vp, P(vp)]),
         "ht_graph_launch": (c_int, [vp, vp]),
@@ -457,6 +465,78 @@ class Batch:
         if getattr(self, "_b", None):
             _check(lib.ht_batch_destroy(self._b))
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Circuit:
+    """ht_circuit: an op sequence applied with fusion of neighbouring ops."""
+
+    def __init__(self, ops=()):
+        c = ctypes.c_void_p()
+        _check(lib.ht_circuit_create(ctypes.byref(c)))
+        self._c = c
+        for op in ops:
+            self.add_op(op)
+
+    def add_unitary(self, targets, U) -> None:
+        U = _c128(U)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_circuit_add_unitary(self._c, len(targets), _ptr(t), _ptr(U)))
+
+    def add_channel(self, targets, kraus) -> None:
+        K = _c128(kraus)
+        if K.ndim == 2:
+            K = K[None]
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        _check(lib.ht_circuit_add_channel(self._c, len(targets), _ptr(t), K.shape[0], _ptr(K)))
+
+    def add_op(self, op) -> None:
+        if op.kind == "unitary":
+            self.add_unitary(op.targets, op.mats[0])
+        else:
+            self.add_channel(op.targets, op.mats)
+
+    def size(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib.ht_circuit_size(self._c, ctypes.byref(n)))
+        return n.value
+
+    def plan(self, picture: int = SCHRODINGER, max_qubits: int = 2) -> int:
+        n = ctypes.c_int64()
+        _check(lib.ht_circuit_plan(self._c, picture, max_qubits, ctypes.byref(n)))
+        return n.value
+
+    def pass_info(self, i: int, transfer: bool = True) -> dict:
+        """Pass i of the last plan: qubits, op indices, transfer matrix."""
+        k = ctypes.c_int()
+        t = np.zeros(3, dtype=np.int32)
+        nops = ctypes.c_int64()
+        _check(lib.ht_circuit_pass_info(self._c, i, ctypes.byref(k), _ptr(t), ctypes.byref(nops), None, None))
+        idx = np.zeros(max(nops.value, 1), dtype=np.int64)
+        S = None
+        if transfer and k.value <= 2:
+            d = 1 << (2 * k.value)
+            S = np.zeros(2 * d * d, dtype=np.float64)
+        _check(lib.ht_circuit_pass_info(self._c, i, None, None, None, _ptr(idx),
+                                        _ptr(S) if S is not None else None))
+        out = {"targets": [int(x) for x in t[:k.value]], "ops": [int(x) for x in idx[:nops.value]]}
+        if S is not None:
+            d = 1 << (2 * k.value)
+            out["transfer"] = S.view(np.complex128).reshape(d, d).copy()
+        return out
+
+    def apply(self, h: "Herm") -> None:
+        _check(lib.ht_circuit_apply(self._c, h.handle))
+
+    def close(self) -> None:
+        if getattr(self, "_c", None):
+            _check(lib.ht_circuit_destroy(self._c))
+            self._c = None
 
     def __del__(self):
         try:

@@ -121,6 +121,37 @@ constexpr int kMaxPauliTerms = 4096;
 
 }  // namespace
 
+ht_status ht_launch_prepared(ht_herm* h, const ht::PreparedOp& op) {
+  ht_device_guard dg(h->device);
+  if (op.k == 2 && op.form == 1) HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 512, h->stream));
+  if (op.form == 2) {
+    double data[512];
+    const int nd = ht::native_op_data(op, data);
+    HT_HIP(ht::launch_upload(h->coef_dev, data, nd, h->stream));
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  if (h->prof) {
+    a = take_event(h);
+    b = take_event(h);
+    if (!a || !b) return ht_fail(HT_EDEVICE, "could not create profiling events");
+    HT_HIP(hipEventRecord(a, h->stream));
+  }
+  if (op.form == 2)
+    HT_HIP(ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
+  else
+    HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
+  if (h->prof) {
+    HT_HIP(hipEventRecord(b, h->stream));
+    const int cls = h->dtype * ht::kClassesPerDtype + ht::conj_class(op.k, op.ncross, op.form);
+    // algorithmic bytes: every stored entry read and written once, or for the
+    // native pass the changing fraction of them
+    double frac = 1.0;
+    if (op.form == 2) frac = (double)__builtin_popcountll(op.active) / (double)(1 << (2 * op.k));
+    h->pending.push_back(ht_pending_event{cls, a, b, 2.0 * frac * (double)h->bytes});
+  }
+  return HT_OK;
+}
+
 extern "C" {
 
 const char* ht_last_error(void) { return g_err.c_str(); }
@@ -412,34 +443,7 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
   if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
                      sizeof msg, ht::tuning().native) != 0)
     return ht_fail(op_error(msg), "%s", msg);
-  ht_device_guard dg(h->device);
-  if (op.k == 2 && op.form == 1) HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 512, h->stream));
-  if (op.form == 2) {
-    double data[512];
-    const int nd = ht::native_op_data(op, data);
-    HT_HIP(ht::launch_upload(h->coef_dev, data, nd, h->stream));
-  }
-  hipEvent_t a = nullptr, b = nullptr;
-  if (h->prof) {
-    a = take_event(h);
-    b = take_event(h);
-    if (!a || !b) return ht_fail(HT_EDEVICE, "could not create profiling events");
-    HT_HIP(hipEventRecord(a, h->stream));
-  }
-  if (op.form == 2)
-    HT_HIP(ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
-  else
-    HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
-  if (h->prof) {
-    HT_HIP(hipEventRecord(b, h->stream));
-    const int cls = h->dtype * ht::kClassesPerDtype + ht::conj_class(op.k, op.ncross, op.form);
-    // algorithmic bytes: every stored entry read and written once, or for the
-    // native pass the changing fraction of them
-    double frac = 1.0;
-    if (op.form == 2) frac = (double)__builtin_popcountll(op.active) / (double)(1 << (2 * op.k));
-    h->pending.push_back(ht_pending_event{cls, a, b, 2.0 * frac * (double)h->bytes});
-  }
-  return HT_OK;
+  return ht_launch_prepared(h, op);
 }
 
 ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,

@@ -51,6 +51,10 @@ struct ht_herm {
   double prof_bytes[2 * ht::kClassesPerDtype] = {};
 };
 
+// Upload the coefficients of a prepared op and enqueue its pass on h's
+// stream (profiled when h's profiling is on).
+ht_status ht_launch_prepared(ht_herm* h, const ht::PreparedOp& op);
+
 // Switch to a device for the lifetime of the guard, if it is not current.
 struct ht_device_guard {
   int prev = -1;

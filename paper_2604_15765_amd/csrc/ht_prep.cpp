@@ -36,6 +36,72 @@ using cplx = std::complex<double>;
 // most 4 units in the last place instead of the product's own rounding.
 constexpr double kUnitSnap = 1.0 / 1125899906842624.0;  // 2^-50
 
+// Fill the native form from the permutation pm and coefficients c (2^k x 2^k,
+// w[u][v] = c[u][v] h[pm[u]][pm[v]]).  Returns 1 when the native form is
+// used, 0 when the op should take a generic form instead (k <= 2 and every
+// entry changes: the native pass would move the same bytes), -1 on error.
+static int native_form(int k, const int* pm, const cplx* c_in, PreparedOp* out, char* err,
+                       size_t errlen) {
+  const int D = 1 << k;
+  out->form = 2;
+  out->active = 0;
+  for (int u = 0; u < D; ++u) out->perm[u] = pm[u];
+  for (int u = D; u < 8; ++u) out->perm[u] = u;
+  for (int u = 0; u < D; ++u)
+    for (int v = 0; v < D; ++v) {
+      cplx c = c_in[u * D + v];
+      const bool fixed = pm[u] == u && pm[v] == v;
+      if (fixed && std::abs(c.real() - 1.0) <= kUnitSnap && std::abs(c.imag()) <= kUnitSnap) c = 1.0;
+      if (!fixed || c != cplx(1.0, 0.0)) out->active |= (uint64_t)1 << (u * D + v);
+      out->coef[2 * (u * D + v)] = c.real();
+      out->coef[2 * (u * D + v) + 1] = c.imag();
+    }
+  // For k <= 2 the native pass pays off only when some entry stays in place
+  // (it then moves fewer bytes); an op that changes every entry (X, Y, ...)
+  // keeps the generic pass, which is exact for permutations too.
+  if (k <= 2 && out->active == (((uint64_t)1 << (D * D)) - 1)) return 0;
+  // k = 3: chunks of whole orbits (first fit, largest orbits first); a cycle
+  // of (u, v) -> (p(u), p(v)) is at most the lcm of two cycle lengths of p
+  // (<= 15), an orbit at most two cycles
+  out->nchunks = 0;
+  out->chunk = 16;
+  std::memset(out->sched, 0, sizeof out->sched);
+  if (k == 3) {
+    std::vector<std::vector<int>> orbits;
+    uint64_t seen = 0;
+    for (int e = 0; e < D * D; ++e) {
+      if (!((out->active >> e) & 1) || ((seen >> e) & 1)) continue;
+      std::vector<int> orb;
+      for (int start : {e, (e % D) * D + e / D})
+        for (int x = start; !((seen >> x) & 1); x = pm[x / D] * D + pm[x % D]) {
+          seen |= (uint64_t)1 << x;
+          orb.push_back(x);
+        }
+      if ((int)orb.size() > 16) out->chunk = 32;
+      orbits.push_back(orb);
+    }
+    std::stable_sort(orbits.begin(), orbits.end(),
+                     [](const std::vector<int>& a, const std::vector<int>& b) { return a.size() > b.size(); });
+    const int cap = 256 / out->chunk;
+    int fill[16] = {0};
+    for (const auto& orb : orbits) {
+      int ch = 0;
+      while (ch < out->nchunks && fill[ch] + (int)orb.size() > out->chunk) ++ch;
+      if (ch == cap) {
+        if (err && errlen) std::snprintf(err, errlen, "internal: native schedule does not fit");
+        return -1;
+      }
+      if (ch == out->nchunks) ++out->nchunks;
+      for (int x : orb) {
+        const int u = x / D, v = x % D;
+        out->sched[ch * out->chunk + fill[ch]++] =
+            (uint16_t)(0x8000 | u | (v << 3) | (pm[u] << 6) | (pm[v] << 9));
+      }
+    }
+  }
+  return 1;
+}
+
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
                int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native) {
   auto fail = [&](const char* msg) {
@@ -108,65 +174,15 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
     mono = seen == (1 << D) - 1;
   }
   if (mono) {
-    out->form = 2;
-    out->active = 0;
-    for (int u = 0; u < D; ++u) out->perm[u] = pm[u];
-    for (int u = D; u < 8; ++u) out->perm[u] = u;
+    cplx c[64];
     for (int u = 0; u < D; ++u)
       for (int v = 0; v < D; ++v) {
-        cplx c = 0.0;
-        for (int a = 0; a < r; ++a) c += A[a][u * D + pm[u]] * std::conj(A[a][v * D + pm[v]]);
-        const bool fixed = pm[u] == u && pm[v] == v;
-        if (fixed && std::abs(c.real() - 1.0) <= kUnitSnap && std::abs(c.imag()) <= kUnitSnap)
-          c = 1.0;
-        if (!fixed || c != cplx(1.0, 0.0)) out->active |= (uint64_t)1 << (u * D + v);
-        out->coef[2 * (u * D + v)] = c.real();
-        out->coef[2 * (u * D + v) + 1] = c.imag();
+        c[u * D + v] = 0.0;
+        for (int a = 0; a < r; ++a) c[u * D + v] += A[a][u * D + pm[u]] * std::conj(A[a][v * D + pm[v]]);
       }
-    // For k <= 2 the native pass pays off only when some entry stays in
-    // place (it then moves fewer bytes); an op that changes every entry (X,
-    // Y, ...) keeps the generic pass, which is exact for permutations too.
-    if (k <= 2 && out->active == (D * D == 64 ? ~(uint64_t)0 : (((uint64_t)1 << (D * D)) - 1)))
-      mono = false;
-  }
-  if (mono) {
-    // chunks of whole orbits (first fit, largest orbits first); a cycle of
-    // (u, v) -> (p(u), p(v)) is at most the lcm of two cycle lengths of p
-    // (<= 15), an orbit at most two cycles
-    out->nchunks = 0;
-    out->chunk = 16;
-    std::memset(out->sched, 0, sizeof out->sched);
-    if (k == 3) {
-      std::vector<std::vector<int>> orbits;
-      uint64_t seen = 0;
-      for (int e = 0; e < D * D; ++e) {
-        if (!((out->active >> e) & 1) || ((seen >> e) & 1)) continue;
-        std::vector<int> orb;
-        for (int start : {e, (e % D) * D + e / D})
-          for (int x = start; !((seen >> x) & 1); x = pm[x / D] * D + pm[x % D]) {
-            seen |= (uint64_t)1 << x;
-            orb.push_back(x);
-          }
-        if ((int)orb.size() > 16) out->chunk = 32;
-        orbits.push_back(orb);
-      }
-      std::stable_sort(orbits.begin(), orbits.end(),
-                       [](const std::vector<int>& a, const std::vector<int>& b) { return a.size() > b.size(); });
-      const int cap = 256 / out->chunk;
-      int fill[16] = {0};
-      for (const auto& orb : orbits) {
-        int ch = 0;
-        while (ch < out->nchunks && fill[ch] + (int)orb.size() > out->chunk) ++ch;
-        if (ch == cap) return fail("internal: native schedule does not fit");
-        if (ch == out->nchunks) ++out->nchunks;
-        for (int x : orb) {
-          const int u = x / D, v = x % D;
-          out->sched[ch * out->chunk + fill[ch]++] =
-              (uint16_t)(0x8000 | u | (v << 3) | (pm[u] << 6) | (pm[v] << 9));
-        }
-      }
-    }
-    return 0;
+    const int st = native_form(k, pm, c, out, err, errlen);
+    if (st < 0) return 1;
+    if (st == 1) return 0;
   }
   if (k == 3)
     return fail("k = 3 is supported for permutation-and-phase operations only (one nonzero "
@@ -192,6 +208,63 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
           out->coef[2 * e] = s.real();
           out->coef[2 * e + 1] = s.imag();
         }
+  return 0;
+}
+
+int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S, int allow_native,
+                     PreparedOp* out, char* err, size_t errlen) {
+  auto fail = [&](const char* msg) {
+    if (err && errlen) std::snprintf(err, errlen, "%s", msg);
+    return 1;
+  };
+  if (!out || !sorted || !S) return fail("NULL argument");
+  if (k != 1 && k != 2) return fail("a transfer matrix acts on 1 or 2 qubits");
+  for (int l = 0; l < k; ++l) {
+    if (sorted[l] < 0 || sorted[l] >= n) return fail("target qubit out of range [0, n)");
+    if (l > 0 && sorted[l] <= sorted[l - 1]) return fail("targets must be ascending");
+  }
+  const int D = 1 << k, DD = D * D;
+  out->k = k;
+  out->ncross = 0;
+  for (int l = 0; l < k; ++l) {
+    out->sorted[l] = sorted[l];
+    if (sorted[l] >= m_eff) ++out->ncross;
+  }
+  // native form if every row of S has one nonzero, at (p(u), p(v)) for one p
+  if (allow_native) {
+    int pm[4] = {-1, -1, -1, -1};
+    bool mono = true;
+    cplx c[16];
+    for (int e = 0; e < DD && mono; ++e) {
+      int f = -1;
+      for (int g = 0; g < DD; ++g) {
+        if (S[2 * (e * DD + g)] == 0.0 && S[2 * (e * DD + g) + 1] == 0.0) continue;
+        if (f >= 0) mono = false;
+        f = g;
+      }
+      if (f < 0) {
+        mono = false;
+        break;
+      }
+      const int u = e / D, v = e % D, fu = f / D, fv = f % D;
+      if ((pm[u] >= 0 && pm[u] != fu) || (pm[v] >= 0 && pm[v] != fv)) mono = false;
+      pm[u] = fu;
+      pm[v] = fv;
+      c[e] = cplx(S[2 * (e * DD + f)], S[2 * (e * DD + f) + 1]);
+    }
+    if (mono) {
+      int seen = 0;
+      for (int u = 0; u < D; ++u) seen |= 1 << pm[u];
+      mono = seen == (1 << D) - 1;
+    }
+    if (mono) {
+      const int st = native_form(k, pm, c, out, err, errlen);
+      if (st < 0) return 1;
+      if (st == 1) return 0;
+    }
+  }
+  out->form = 1;
+  for (int i = 0; i < 2 * DD * DD; ++i) out->coef[i] = S[i];
   return 0;
 }
 

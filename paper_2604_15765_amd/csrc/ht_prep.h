@@ -35,4 +35,12 @@ struct PreparedOp {
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
                int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native = 1);
 
+// Prepare a 1- or 2-qubit map given by its transfer matrix S (4^k x 4^k,
+// row-major, interleaved complex; w = S vec(h) with vec row-major over local
+// indices whose bit l belongs to sorted[l], ascending).  Uses the native
+// form when S has one nonzero per row at (p(u), p(v)) for one permutation p
+// and allow_native; else form 1.
+int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S, int allow_native,
+                     PreparedOp* out, char* err, size_t errlen);
+
 }  // namespace ht
