@@ -123,7 +123,8 @@ def run_batched(args):
     del graphs, graphed
 
     # 4. autotuned: tile edge per n and launch shape picked on a sample of the
-    # queued batch, operators created with the chosen edges
+    # queued batch, operators created with the chosen edges; then the same
+    # with each operator's ops fused into 2-qubit passes
     tuned_cfg = batch.autotune(args.tune_sample)
     log(f"[batched] autotune: {tuned_cfg}")
     edges = dict(tile)
@@ -149,6 +150,42 @@ def run_batched(args):
     t_tuned = time.perf_counter() - t0
     log(f"[batched] tuned edges, plain launches: {t_tplain:.3f} s; tuned batch: {t_tuned:.3f} s")
     same_tuned = all(torch.equal(a.buffer, b.buffer) for a, b in zip(tplain, tuned))
+    del tplain
+    fused = fresh(edges)
+    fbatch = ht.Batch(threads=tuned_cfg["threads"], wg_per_cu=tuned_cfg["wg_per_cu"],
+                      lds_max_bytes=tuned_cfg["lds_max_bytes"], fuse_qubits=2)
+    for h, (_, _, ops) in zip(fused, work):
+        for op in ops:
+            fbatch.add_op(h, op)
+    fbatch.run()  # plans and composes every operator's passes (host), then runs
+    torch.cuda.synchronize()
+    fused2 = fresh(edges)
+    fbatch.clear()
+    for h, (_, _, ops) in zip(fused2, work):
+        for op in ops:
+            fbatch.add_op(h, op)
+    t0 = time.perf_counter()
+    fbatch.run()
+    torch.cuda.synchronize()
+    t_fused_total = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fbatch.run()  # fused lists cached: device time plus table upload
+    torch.cuda.synchronize()
+    t_fused = time.perf_counter() - t0
+    log(f"[batched] fused batch: {t_fused:.3f} s (with planning {t_fused_total:.3f} s)")
+    devs = []
+    for a, b, (n, _, _) in zip(fused, tuned, work):
+        if n <= 8 and len(devs) < 256:
+            da, db = a.to_dense(), b.to_dense()
+            devs.append(float(np.linalg.norm(da - db) / np.linalg.norm(db)))
+    fused_dev = max(devs)
+    npasses = 0
+    for (_, _, ops) in work:
+        c = ht.Circuit(ops)
+        npasses += c.plan(ht.SCHRODINGER, 2)
+        c.close()
+    log(f"[batched] fused: {npasses} passes for {nops} ops; max deviation from unfused {fused_dev:.2e}")
 
     # oracle on a stratified sample: the first `per_n` operators of each n
     worst = 0.0
@@ -175,6 +212,9 @@ def run_batched(args):
                   "gate_conj_per_s": nops / t_tuned, "autotune": tuned_cfg,
                   "speedup_vs_plain_same_edges": t_tplain / t_tuned,
                   "speedup_vs_plain_default_edges": t_plain / t_tuned},
+        "fused": {"s": t_fused, "s_with_planning": t_fused_total, "circuits_per_s": args.count / t_fused,
+                  "gate_conj_per_s": nops / t_fused, "speedup_vs_plain_default_edges": t_plain / t_fused,
+                  "passes": npasses, "max_rel_frobenius_vs_unfused_n_le_8": fused_dev},
         "speedup_vs_plain": t_plain / t_batch, "speedup_vs_graph": t_graph / t_batch,
         "bitwise_equal": {"graph": same_graph, "batched": same_batch, "tuned_vs_plain": same_tuned},
         "oracle_check": {"operators": checked, "max_rel_frobenius": worst, "tolerance": 1e-12},
@@ -227,12 +267,23 @@ def run_serve(args):
                                      max_medium_active=args.max_medium_active,
                                      chunk_ops=args.chunk_ops, large_chunk_ops=args.large_chunk_ops)
         log(f"[serve]   continuous: {cont}")
+        fused, v_fused = _serve_stream(ht, reqs, rate, budget_bytes=args.budget_gb << 30,
+                                       max_active=args.max_active, batch_max_qubits=args.batch_max_qubits,
+                                       medium_max_qubits=args.medium_max_qubits,
+                                       max_medium_active=args.max_medium_active,
+                                       chunk_ops=args.chunk_ops, large_chunk_ops=args.large_chunk_ops,
+                                       fuse_qubits=2)
+        log(f"[serve]   continuous, fused: {fused}")
         fifo, v_fifo = _serve_stream(ht, reqs, rate, budget_bytes=args.budget_gb << 30, fifo=1)
         log(f"[serve]   one at a time: {fifo}")
+        dev = max(abs(a - b) / max(1.0, abs(b)) for a, b, r in zip(v_fused, v_fifo, reqs))
         results.append({"rate": rate, "requests": len(reqs), "ops": nops, "continuous": cont,
-                        "plain_fifo": fifo, "equal_results": v_cont == v_fifo,
+                        "continuous_fused": fused, "plain_fifo": fifo, "equal_results": v_cont == v_fifo,
+                        "fused_max_rel_dev": dev,
                         "throughput_ratio": cont["circuits_per_s"] / fifo["circuits_per_s"],
-                        "p99_ratio": fifo["p99_s"] / cont["p99_s"]})
+                        "p99_ratio": fifo["p99_s"] / cont["p99_s"],
+                        "fused_throughput_ratio": fused["circuits_per_s"] / fifo["circuits_per_s"],
+                        "fused_p99_ratio": fifo["p99_s"] / fused["p99_s"]})
     print(json.dumps({"bench": "serve", "results": results,
                       "workload": "Poisson arrivals; n = floor(exp(U(ln 6, ln 17))); 10..300 mixed ops; "
                                   "c128/c64 50/50; half with a 64-term Pauli-sum readout"}), flush=True)

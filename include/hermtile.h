@@ -236,8 +236,10 @@ ht_status ht_batch_destroy(ht_batch* b);
 /* Schedule parameters: "threads" (64..1024, power of two, default 256) per
  * workgroup; "wg_per_cu" (1..32, default 2) workgroups per compute unit;
  * "lds_max_bytes" (0..163584 = 160 KiB less the kernel's own LDS, default
- * 65536): operators up to this size run in LDS (0 disables LDS staging).
- * HT_EINVAL for an unknown name or value. */
+ * 65536): operators up to this size run in LDS (0 disables LDS staging);
+ * "fuse_qubits" (0, 1 or 2, default 0): run each operator's queued ops
+ * fused into passes on at most that many qubits, as ht_circuit does (0: one
+ * pass per op).  HT_EINVAL for an unknown name or value. */
 ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value);
 
 /* Queue one op for operator h; arguments as ht_apply_unitary /
@@ -371,6 +373,8 @@ typedef struct {
   int max_large_active;  /* large requests running passes at once */
   int medium_max_qubits; /* n <= this (and > batch_max_qubits): medium lane */
   int max_medium_active; /* medium requests running passes at once */
+  int fuse_qubits;       /* 0: one pass per op; 1, 2: a request's ops fused into
+                            passes on at most that many qubits (as ht_circuit) */
 } ht_server_config;
 
 /* Defaults: 200 GiB budget, 32 active, batched rounds up to n = 8 (an

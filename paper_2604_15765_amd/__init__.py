@@ -583,7 +583,8 @@ class ServerConfig(ctypes.Structure):
                 ("large_chunk_ops", ctypes.c_int), ("tile_log2", ctypes.c_int), ("fifo", ctypes.c_int),
                 ("batch_threads", ctypes.c_int), ("batch_wg_per_cu", ctypes.c_int),
                 ("lds_max_bytes", ctypes.c_size_t), ("max_large_active", ctypes.c_int),
-                ("medium_max_qubits", ctypes.c_int), ("max_medium_active", ctypes.c_int)]
+                ("medium_max_qubits", ctypes.c_int), ("max_medium_active", ctypes.c_int),
+                ("fuse_qubits", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):

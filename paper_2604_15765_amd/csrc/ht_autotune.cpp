@@ -71,17 +71,9 @@ class Tuner {
   ht_status prepare(std::vector<Trial>& trials) {
     char msg[256];
     for (auto& tr : trials) {
-      tr.ops.clear();
-      tr.coefs.clear();
       const int n = tr.e->h->n;
-      const int m = std::min(n, tr.m_req);
-      for (const auto& r : tr.e->raw) {
-        ht::PreparedOp op;
-        if (ht::prepare_op(n, m, r.k, r.targets, r.r, tr.e->mats.data() + r.mat_off, r.heisenberg,
-                           &op, msg, sizeof msg, ht::tuning().native) != 0)
-          return ht_fail(HT_EINVAL, "autotune: %s", msg);
-        ht::append_batch_op(op, tr.ops, tr.coefs);
-      }
+      if (ht::entry_ops(*tr.e, std::min(n, tr.m_req), b_->fuse_q, tr.ops, tr.coefs, msg, sizeof msg) != 0)
+        return ht_fail(HT_EINVAL, "autotune: %s", msg);
     }
     return HT_OK;
   }

@@ -12,12 +12,41 @@
 #include "ht_internal.h"
 #include "ht_batch_runner.h"
 #include "ht_batch_state.h"
+#include "ht_fuse.h"
 #include "ht_prep.h"
 
 struct ht_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+namespace ht {
+
+int entry_ops(const ht_batch::Entry& e, int m_eff, int fuse_q, std::vector<BatchOp>& ops,
+              std::vector<double>& coefs, char* err, size_t errlen) {
+  ops.clear();
+  coefs.clear();
+  std::vector<FuseOp> fops(e.raw.size());
+  std::vector<const FuseOp*> seq(e.raw.size());
+  for (size_t i = 0; i < e.raw.size(); ++i) {
+    const ht_batch::RawOp& r = e.raw[i];
+    FuseOp& f = fops[i];
+    f.k = r.k;
+    f.targets[0] = r.targets[0];
+    f.targets[1] = r.targets[1];
+    f.targets[2] = -1;
+    f.r = r.r;
+    f.adj = r.heisenberg;
+    f.mats = e.mats.data() + r.mat_off;
+    seq[i] = &f;
+  }
+  std::vector<PreparedOp> prepared;
+  if (fuse_ops(seq, fuse_q, e.h->n, m_eff, tuning().native, &prepared, err, errlen) != 0) return 1;
+  for (const PreparedOp& op : prepared) append_batch_op(op, ops, coefs);
+  return 0;
+}
+
+}  // namespace ht
 
 namespace {
 
@@ -49,6 +78,7 @@ ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, cons
   }
   auto& en = b->entries[e];
   ht::append_batch_op(op, en.ops, en.coefs);
+  en.fused_q = -1;  // the fused list is stale
   const int D = 1 << k;
   ht_batch::RawOp raw{};
   raw.k = k;
@@ -89,6 +119,9 @@ ht_status ht_batch_set_param(ht_batch* b, const char* name, int64_t value) {
   } else if (k == "wg_per_cu") {
     if (value < 1 || value > 32) return ht_fail(HT_EINVAL, "wg_per_cu must be in [1, 32]");
     b->sched.wg_per_cu = (int)value;
+  } else if (k == "fuse_qubits") {
+    if (value < 0 || value > 2) return ht_fail(HT_EINVAL, "fuse_qubits must be 0, 1 or 2");
+    b->fuse_q = (int)value;
   } else if (k == "lds_max_bytes") {
     if (value < 0 || value > kBatchLdsMax)
       return ht_fail(HT_EINVAL, "lds_max_bytes must be in [0, %lld]", (long long)kBatchLdsMax);
@@ -139,10 +172,22 @@ ht_status ht_batch_run(ht_batch* b, void* hip_stream) {
     }
   std::vector<ht::BatchItem> items;
   items.reserve(b->entries.size());
-  for (const auto& e : b->entries)
-    items.push_back(ht::BatchItem{e.h->buf, e.h->bytes, e.h->n, e.h->m, e.h->dtype, e.ops.data(),
-                                  (uint32_t)e.ops.size(), e.coefs.data(),
-                                  (uint32_t)e.coefs.size()});
+  char msg[256];
+  for (auto& e : b->entries) {
+    const std::vector<ht::BatchOp>* ops = &e.ops;
+    const std::vector<double>* coefs = &e.coefs;
+    if (b->fuse_q > 0) {
+      if (e.fused_q != b->fuse_q) {
+        if (ht::entry_ops(e, e.h->m, b->fuse_q, e.fused_ops, e.fused_coefs, msg, sizeof msg) != 0)
+          return ht_fail(HT_EINVAL, "fusing the ops of an operator: %s", msg);
+        e.fused_q = b->fuse_q;
+      }
+      ops = &e.fused_ops;
+      coefs = &e.fused_coefs;
+    }
+    items.push_back(ht::BatchItem{e.h->buf, e.h->bytes, e.h->n, e.h->m, e.h->dtype, ops->data(),
+                                  (uint32_t)ops->size(), coefs->data(), (uint32_t)coefs->size()});
+  }
   HT_HIP(b->runner.run(items, b->sched, b->num_cu, s));
   return HT_OK;
 }

@@ -26,12 +26,17 @@ struct ht_batch {
     std::vector<double> coefs;
     std::vector<RawOp> raw;
     std::vector<double> mats;
+    // fused op list (ops and coefficients) for fuse_q, rebuilt when stale
+    int fused_q = -1;
+    std::vector<ht::BatchOp> fused_ops;
+    std::vector<double> fused_coefs;
   };
   std::vector<Entry> entries;
   std::unordered_map<ht_herm*, size_t> index;
   int device = 0;
   int num_cu = 256;
   ht::BatchSchedule sched;
+  int fuse_q = 0;  // 0: one pass per op; 1, 2: fused passes on at most that many qubits
   ht::BatchRunner runner;
 };
 
@@ -52,5 +57,11 @@ inline void append_batch_op(const PreparedOp& op, std::vector<BatchOp>& ops,
   coefs.insert(coefs.end(), op.coef, op.coef + op_coef_doubles(op.k, op.form));
   ops.push_back(bo);
 }
+
+// The op list of entry e for tile exponent m_eff (the operator's own or a
+// candidate's) with fusion on at most fuse_q qubits (0: the ops as queued,
+// prepared again).  Returns 0 or nonzero with a message.
+int entry_ops(const ht_batch::Entry& e, int m_eff, int fuse_q, std::vector<BatchOp>& ops,
+              std::vector<double>& coefs, char* err, size_t errlen);
 
 }  // namespace ht

@@ -32,6 +32,7 @@
 #include "ht_batch_runner.h"
 #include "ht_handle.h"
 #include "ht_batch_state.h"
+#include "ht_fuse.h"
 #include "ht_internal.h"
 #include "ht_prep.h"
 
@@ -447,6 +448,7 @@ void ht_server_config_default(ht_server_config* c) {
   c->batch_max_qubits = 8;
   c->medium_max_qubits = 12;
   c->max_medium_active = 4;
+  c->fuse_qubits = 0;
 }
 
 ht_status ht_server_create(const ht_server_config* cfg, ht_server** out) {
@@ -460,6 +462,8 @@ ht_status ht_server_create(const ht_server_config* cfg, ht_server** out) {
     return ht_fail(HT_EINVAL, "tile_log2 out of range");
   if (cfg->max_large_active < 1 || cfg->max_medium_active < 1)
     return ht_fail(HT_EINVAL, "lane concurrency limits must be positive");
+  if (cfg->fuse_qubits < 0 || cfg->fuse_qubits > 2)
+    return ht_fail(HT_EINVAL, "fuse_qubits must be 0, 1 or 2");
   ht_server* s = new ht_server();
   s->cfg = *cfg;
   if (s->cfg.fifo) s->cfg.max_active = 1;
@@ -524,6 +528,7 @@ ht_status ht_server_submit(ht_server* s, const ht_request* q, int64_t* id) {
   if (r->bytes + r->gbytes > s->cfg.budget_bytes)
     return ht_fail(HT_EINVAL, "request needs %zu bytes, more than the budget", r->bytes + r->gbytes);
   size_t mat_off = 0;
+  std::vector<ht::FuseOp> fops(q->nops);
   for (int i = 0; i < q->nops; ++i) {
     const int k = q->op_k[i];
     if (k != 1 && k != 2) return ht_fail(HT_EINVAL, "op %d: k must be 1 or 2 in a request", i);
@@ -532,8 +537,26 @@ ht_status ht_server_submit(ht_server* s, const ht_request* q, int64_t* id) {
     if (ht::prepare_op(r->n, r->m, k, q->op_targets + 2 * i, q->op_r[i], q->op_mats + mat_off,
                        q->picture == HT_HEISENBERG, &op, msg, sizeof msg, ht::tuning().native) != 0)
       return ht_fail(HT_EINVAL, "op %d: %s", i, msg);
+    ht::FuseOp& f = fops[i];
+    f.k = k;
+    f.targets[0] = q->op_targets[2 * i];
+    f.targets[1] = k > 1 ? q->op_targets[2 * i + 1] : -1;
+    f.targets[2] = -1;
+    f.r = q->op_r[i];
+    f.adj = q->picture == HT_HEISENBERG ? 1 : 0;
+    f.mats = q->op_mats + mat_off;
     mat_off += (size_t)2 * q->op_r[i] * (1u << (2 * k));
-    ht::append_batch_op(op, r->ops, r->coefs);
+    if (s->cfg.fuse_qubits == 0) ht::append_batch_op(op, r->ops, r->coefs);
+  }
+  if (s->cfg.fuse_qubits > 0) {
+    std::vector<const ht::FuseOp*> seq(fops.size());
+    for (size_t i = 0; i < fops.size(); ++i) seq[i] = &fops[i];
+    std::vector<ht::PreparedOp> prepared;
+    char msg[256];
+    if (ht::fuse_ops(seq, s->cfg.fuse_qubits, r->n, r->m, ht::tuning().native, &prepared, msg,
+                     sizeof msg) != 0)
+      return ht_fail(HT_EINVAL, "fusing the request's ops: %s", msg);
+    for (const ht::PreparedOp& op : prepared) ht::append_batch_op(op, r->ops, r->coefs);
   }
   for (int t = 0; t < q->nterms; ++t) {
     uint32_t x = 0, z = 0;

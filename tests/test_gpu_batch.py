@@ -187,3 +187,33 @@ def test_autotune_rejects_an_empty_batch(ht):
     with pytest.raises(ht.HermError):
         b.autotune()
     b.close()
+
+
+def test_fused_batch_equals_fused_circuits(ht):
+    """fuse_qubits = 2: each operator's ops run as the fused passes a circuit
+    plans (bitwise equal to ht_circuit_apply on a copy), fewer passes than
+    ops, and the oracle's result."""
+    rng = synth.make_rng(1300)
+    batch = ht.Batch(fuse_qubits=2)
+    rows = []
+    for i in range(20):
+        n = int(rng.integers(2, 9))
+        m = int(rng.choice([2, 3, 5]))
+        H = synth.random_hermitian_dense(n, rng)
+        ops = _random_circuit(n, int(rng.integers(10, 40)), rng)
+        a = ht.Herm(n, m).init_dense(H)
+        b = ht.Herm(n, m).init_dense(H)
+        for op in ops:
+            batch.add_op(a, op)
+        c = ht.Circuit(ops)
+        npass = c.plan(0, 2)
+        c.apply(b)
+        rows.append((a, b, H, ops, npass, c))
+    batch.run()
+    torch.cuda.synchronize()
+    assert sum(r[4] for r in rows) < sum(len(r[3]) for r in rows)
+    for a, b, H, ops, npass, c in rows:
+        assert np.array_equal(a.read_raw(), b.read_raw()), (a.n, npass, len(ops))
+        assert rel(a.to_dense(), oracle.apply_ops(H, ops)) <= 1e-12
+        c.close()
+    batch.close()

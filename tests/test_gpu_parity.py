@@ -317,6 +317,30 @@ def test_full_size_sampled_blocks(ht, n):
     assert abs(h.trace() - 1.0) < 1e-12
 
 
+def test_largest_operator(ht):
+    """The largest c128 operator that fits one MI355X: n = 17 (131072 x 131072,
+    137.5 GB of tiles, element offsets beyond 2^32), with ops whose targets
+    select the farthest tiles, on sampled blocks, plus the trace."""
+    n = 17
+    free, _ = torch.cuda.mem_get_info()
+    if free < ht.storage_bytes(n, 5) + (8 << 30):
+        pytest.skip("needs about 146 GB of free device memory")
+    rng = synth.make_rng(917)
+    h = ht.Herm(n, 5)
+    h.init_lowrank(synth.ginibre_factor(n, 8, rng))
+    h.scale(1.0 / h.trace())
+    assert h.nbytes == 137_472_507_904
+    ops = [synth.random_ops.unitary_op([n - 1], synth.haar_unitary(2, rng)),
+           synth.random_ops.channel_op([n - 2, 0], synth.random_kraus_set(2, 2, rng)),
+           synth.random_ops.unitary_op([n - 1, n - 3], synth.cnot_matrix())]
+    for i, op in enumerate(ops):
+        e = _sampled_op_check(h, op, i % 2 if op.kind == "unitary" else 0, n, rng, nblocks=800)
+        assert e <= TOL, (op.targets, e)
+    assert abs(h.trace() - 1.0) < 1e-12
+    h.close()
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------- complex64
 
 C64_EPS = 2.0 ** -24  # unit roundoff of float32 (round to nearest)

@@ -101,3 +101,22 @@ def test_server_rejects_bad_requests(ht):
     (d,) = srv.poll()
     assert d["id"] == ok and d["status"] == 0 and abs(d["value"] - 1.0) < 1e-12
     srv.close()
+
+
+def test_server_with_fusion(ht):
+    """Requests fused into 2-qubit passes: the same value alone, in the mix
+    and one at a time (bitwise), and the oracle's value within tolerance."""
+    reqs = _requests(81, 20, [3, 5, 6, 7, 8, 9]) + _requests(82, 2, [12])
+    cfg = dict(batch_max_qubits=7, medium_max_qubits=9, chunk_ops=8, large_chunk_ops=2, fuse_qubits=2)
+    alone, _ = _serve(ht, [reqs[1]], **cfg)
+    mixed, _ = _serve(ht, reqs, **cfg)
+    fifo, _ = _serve(ht, reqs, fifo=1, fuse_qubits=2)
+    plain, _ = _serve(ht, reqs, fifo=1)
+    assert alone[0] == mixed[1]
+    assert mixed == fifo
+    for r, v, p in zip(reqs, mixed, plain):
+        if r["dtype"] == "c128":
+            assert abs(v - p) <= 1e-12 * max(1.0, abs(p))
+            if r["n"] <= 9:
+                want = _oracle_value(r)
+                assert abs(v - want) <= 1e-12 * max(1.0, abs(want)), (r["n"], v, want)
