@@ -457,8 +457,10 @@ const char* ht_kernel_class_name(int idx);
  * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
  * 0): 0 = each wave processes whole tile groups, 1 = the patches of a group
  * are spread over neighbouring waves.  "native" (0 or 1, default 1): the
- * native pass for permutation-and-phase operations.  HT_EINVAL for an
- * unknown name or value. */
+ * native pass for permutation-and-phase operations.  "interleave" (0 or 1,
+ * default 1): the order in which a lane walks its patches of a tile group,
+ * 1 alternating column and row patches (whole cache lines of 8-byte entries
+ * in mirrored tiles too).  HT_EINVAL for an unknown name or value. */
 ht_status ht_set_tuning(const char* name, int64_t value);
 
 /* Pure host function (no GPU): the per-op preparation the library performs

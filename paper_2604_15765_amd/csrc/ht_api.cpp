@@ -596,6 +596,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().order = (int)value;
     return HT_OK;
   }
+  if (k == "interleave") {
+    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "interleave must be 0 or 1");
+    ht::tuning().interleave = (int)value;
+    return HT_OK;
+  }
   if (k == "native") {
     if (value != 0 && value != 1) return ht_fail(HT_EINVAL, "native must be 0 or 1");
     ht::tuning().native = (int)value;

@@ -34,8 +34,9 @@ __device__ void batch_pass(S2<T>* base, int n, int m, const BatchOp& op,
 #pragma unroll
     for (int i = 0; i < 2 * Coef<K, FORM>::NE; ++i) cf.c[i] = coefs[op.coef_off + i];
   }
-  // base may point to LDS or to global memory (generic addressing)
-  const DirectMem<T, 0> mem{base};
+  // base may point to LDS or to global memory (generic addressing); entries
+  // held as FP64 (the kernel's budget at 1024 threads is 128 VGPRs)
+  const DirectMem<T, 0, true> mem{base};
   for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
     GroupCtx<C> gc;
     group_ctx<K, C>(grp, g, gc);

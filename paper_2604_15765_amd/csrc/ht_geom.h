@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ht {
 
 #define HT_HD __host__ __device__ inline
@@ -100,9 +102,14 @@ HT_HD void tri_decode(uint64_t g, uint32_t& ti, uint32_t& tj) {
 }
 
 // Blocks in flight per lane: 16 entry loads for k = 1 (4 blocks) and for
-// k = 2 (one block) -- the depth at which an in-place stream on MI355X
-// reaches its best bandwidth.
-constexpr int conj_unroll(int K) { return K == 1 ? 4 : 1; }
+// k = 2 (one block) of 16-byte entries -- 256 bytes per lane, the depth at
+// which an in-place stream on MI355X reaches its best bandwidth.  8-byte
+// entries stay in their storage type until their block is computed, which
+// leaves room for two k = 2 blocks (measured +2..8 %; for k = 1 eight blocks
+// measured slower than four).
+constexpr int conj_unroll(int K, int entry_bytes = 16) {
+  return K == 1 ? 4 : (entry_bytes == 8 ? 2 : 1);
+}
 
 // Geometry of one conjugation pass with K targets of which C are cross.
 template <int K, int C>
@@ -111,6 +118,7 @@ struct ConjGeom {
   int m;                       // effective tile exponent
   int F;                       // free bits per tile dimension: m - KI
   int s;                       // patch exponent: min(3, F)
+  bool ilv;                    // alternate the high bits of p and q (lane_block)
   int ipos[KI > 0 ? KI : 1];   // intra target bits, ascending, < m
   int cpos[C > 0 ? C : 1];     // cross targets minus m, ascending
   uint32_t jobs;               // 64-block patches per group: ceil(4^F / 64)
@@ -143,12 +151,26 @@ HT_HD uint32_t ins_cross(uint32_t t, uint32_t X, const int* cpos) {
 }
 
 // Block index b (0 <= b < 4^F) -> base indices (pidx, qidx) in [0, 2^F):
-// bits [0,s) -> q low, [s,2s) -> p low, [2s,F+s) -> q high, [F+s,2F) -> p high.
-HT_HD void lane_block(uint32_t b, int F, int s, uint32_t& pidx, uint32_t& qidx) {
+// bits [0,s) -> q low, [s,2s) -> p low; the high bits either in two runs
+// ([2s,F+s) -> q high, [F+s,2F) -> p high) or, with ilv, alternating
+// (q high bit 0, p high bit 0, q high bit 1, ...), so that four consecutive
+// patches cover 16 columns of 16 rows: whole 128-byte lines of 8-byte
+// entries both in a stored tile (rows p) and in a mirrored one (rows q).
+HT_HD void lane_block(uint32_t b, int F, int s, bool ilv, uint32_t& pidx, uint32_t& qidx) {
   const uint32_t ms = (1u << s) - 1u;
-  const uint32_t mh = (1u << (F - s)) - 1u;
-  qidx = (b & ms) | (((b >> (2 * s)) & mh) << s);
-  pidx = ((b >> s) & ms) | ((b >> (F + s)) << s);
+  if (!ilv) {
+    const uint32_t mh = (1u << (F - s)) - 1u;
+    qidx = (b & ms) | (((b >> (2 * s)) & mh) << s);
+    pidx = ((b >> s) & ms) | ((b >> (F + s)) << s);
+    return;
+  }
+  qidx = b & ms;
+  pidx = (b >> s) & ms;
+  const uint32_t hi = b >> (2 * s);
+  for (int i = 0; i < F - s; ++i) {
+    qidx |= ((hi >> (2 * i)) & 1u) << (s + i);
+    pidx |= ((hi >> (2 * i + 1)) & 1u) << (s + i);
+  }
 }
 
 // Per-group context: where each of the 2^C x 2^C tiles lives and whether it
@@ -269,7 +291,9 @@ struct native2<float> {
   typedef float type __attribute__((ext_vector_type(2)));
 };
 
-template <typename T, int MODE = 0>
+// WIDE: hold loaded 8-byte entries as FP64 too (for kernels whose register
+// budget is tight, and where it measured faster).
+template <typename T, int MODE = 0, bool WIDE = false>
 struct DirectMem {
   typename store2<T>::type* __restrict__ h;
   using V = typename native2<T>::type;
@@ -278,13 +302,38 @@ struct DirectMem {
     return reinterpret_cast<const V*>(reinterpret_cast<const char*>(h + tb) +
                                       (uint32_t)(off * (uint32_t)sizeof(V)));
   }
-  HT_HD cd load(uint64_t tb, uint32_t off) const {
-    V v;
+  HT_HD V load_v(uint64_t tb, uint32_t off) const {
     if constexpr ((MODE & 1) != 0)
-      v = __builtin_nontemporal_load(at(tb, off));
+      return __builtin_nontemporal_load(at(tb, off));
     else
-      v = *at(tb, off);
+      return *at(tb, off);
+  }
+  HT_HD cd load(uint64_t tb, uint32_t off) const {
+    const V v = load_v(tb, off);
     return {(double)v.x, (double)v.y};
+  }
+  // A loaded entry as a lane holds it until its block is computed: 8-byte
+  // entries stay in the storage type (half the registers, so twice the
+  // blocks in flight), 16-byte ones are kept as FP64 values, conjugated at
+  // once when read through a mirror.
+  static constexpr bool kNarrow = sizeof(T) == 4 && !WIDE;
+  struct Narrow {
+    V v;
+  };
+  using R = typename std::conditional<kNarrow, Narrow, cd>::type;
+  HT_HD R load_x(uint64_t tb, uint32_t off, bool cj) const {
+    const V v = load_v(tb, off);
+    if constexpr (kNarrow)
+      return Narrow{v};
+    else
+      return cd{(double)v.x, cj ? -(double)v.y : (double)v.y};
+  }
+  // FP64 value of a held entry (cj: read through a mirror)
+  HT_HD static cd widen(const R& r, bool cj) {
+    if constexpr (kNarrow)
+      return cd{(double)r.v.x, cj ? -(double)r.v.y : (double)r.v.y};
+    else
+      return r;
   }
   HT_HD void store(uint64_t tb, uint32_t off, cd w) const {
     V v;
@@ -310,7 +359,7 @@ template <int K, int C>
 HT_HD BlockPos block_pos(const ConjGeom<K, C>& g, const GroupCtx<C>& gc, uint32_t b, bool valid) {
   constexpr int KI = K - C;
   uint32_t pidx, qidx;
-  lane_block(b, g.F, g.s, pidx, qidx);
+  lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
   BlockPos r;
   r.p = deposit_free<KI>(pidx, g.ipos);
   r.q = deposit_free<KI>(qidx, g.ipos);
@@ -319,10 +368,11 @@ HT_HD BlockPos block_pos(const ConjGeom<K, C>& g, const GroupCtx<C>& gc, uint32_
 }
 
 // Read the block's 2^k x 2^k entries (row-major, local bits in ascending
-// target order); mirrored tiles are read transposed and conjugated.
+// target order); mirrored tiles are read transposed and their entries
+// conjugated (for 8-byte entries when the block is widened, block_widen).
 template <int K, int C, typename Mem>
 HT_HD void block_load(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
-                      const BlockPos& bp, cd (&x)[(1 << K) * (1 << K)]) {
+                      const BlockPos& bp, typename Mem::R (&x)[(1 << K) * (1 << K)]) {
   constexpr int D = 1 << K;
   constexpr int KI = K - C;
   constexpr int IM = (1 << KI) - 1;
@@ -336,22 +386,34 @@ HT_HD void block_load(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>
       const int X = u >> KI, Y = v >> KI;
       const bool d = gc.dir[X][Y];
       const uint32_t off = d ? (ru << m) + cv : (cv << m) + ru;
-      cd val = mem.load(gc.tbase[X][Y], off);
-      if (!d) val.im = -val.im;
-      x[u * D + v] = val;
+      x[u * D + v] = mem.load_x(gc.tbase[X][Y], off, !d);
     }
   }
+}
+
+// The loaded block in FP64, mirrored entries conjugated.
+template <int K, int C, typename Mem>
+HT_HD void block_widen(const GroupCtx<C>& gc, const typename Mem::R (&x)[(1 << K) * (1 << K)],
+                       cd (&w)[(1 << K) * (1 << K)]) {
+  constexpr int D = 1 << K;
+  constexpr int KI = K - C;
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+#pragma unroll
+    for (int v = 0; v < D; ++v) w[u * D + v] = Mem::widen(x[u * D + v], !gc.dir[u >> KI][v >> KI]);
 }
 
 // Apply the operation to the loaded block and write the results back.
 template <int K, int C, int FORM, typename Mem>
 HT_HD void block_update_store(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
                               const Coef<K, FORM>& cf, const BlockPos& bp,
-                              const cd (&x)[(1 << K) * (1 << K)]) {
+                              const typename Mem::R (&xr)[(1 << K) * (1 << K)]) {
   constexpr int KI = K - C;
   constexpr int IM = (1 << KI) - 1;
   const int m = g.m;
   const uint32_t p = bp.p, q = bp.q;
+  cd x[(1 << K) * (1 << K)];
+  block_widen<K, C, Mem>(gc, xr, x);
   block_apply<K, FORM>(x, cf, [&](int u, int v, cd w) {
     const uint32_t ru = p + dep_intra<KI>(u & IM, g.ipos);
     const uint32_t cv = q + dep_intra<KI>(v & IM, g.ipos);
@@ -390,7 +452,7 @@ HT_HD void conj_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const GroupC
   if (job_end > g.jobs) job_end = g.jobs;
   for (uint32_t job = job_begin; job < job_end; job += JU) {
     BlockPos bp[JU];
-    cd x[JU][D * D];
+    typename Mem::R x[JU][D * D];
 #pragma unroll
     for (int j = 0; j < JU; ++j) {
       const uint32_t b = (job + j) * 64u + lane;
@@ -406,12 +468,14 @@ HT_HD void conj_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const GroupC
 // Geometry of a pass for an n-qubit operator with effective tile exponent m
 // and ascending targets sorted[0..K) of which the last C are cross targets.
 template <int K, int C>
-HT_HD ConjGeom<K, C> make_geom(int n, int m, const int* sorted) {
+// ilv: the alternating patch order of lane_block.
+HT_HD ConjGeom<K, C> make_geom(int n, int m, const int* sorted, bool ilv = false) {
   ConjGeom<K, C> g{};
   constexpr int KI = K - C;
   g.m = m;
   g.F = m - KI;
   g.s = g.F < 3 ? g.F : 3;
+  g.ilv = ilv;
   for (int l = 0; l < KI; ++l) g.ipos[l] = sorted[l];
   for (int l = 0; l < C; ++l) g.cpos[l] = sorted[KI + l] - m;
   const uint32_t nblk = 1u << (2 * g.F);

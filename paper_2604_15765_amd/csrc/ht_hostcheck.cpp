@@ -31,6 +31,14 @@ struct CheckedMem {
     if (rc) rc[e]++;
     return ht::load_c<double>(h + tb, off);
   }
+  // held entries as the GPU holds 16-byte ones: FP64, conjugated at load
+  using R = ht::cd;
+  R load_x(uint64_t tb, uint32_t off, bool cj) const {
+    ht::cd v = load(tb, off);
+    if (cj) v.im = -v.im;
+    return v;
+  }
+  static ht::cd widen(const R& r, bool) { return r; }
   void store(uint64_t tb, uint32_t off, ht::cd v) const {
     const uint64_t e = tb + off;
     if (e >= nelems) {
@@ -43,9 +51,9 @@ struct CheckedMem {
 };
 
 template <int JU, int K, int C, int FORM>
-void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int order,
+void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int order, bool ilv,
          uint64_t* lanes_run) {
-  ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, op.sorted);
+  ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, op.sorted, ilv);
   ht::Coef<K, FORM> cf;
   if constexpr (K == 2 && FORM == 1) {
     cf.p = op.coef;
@@ -68,9 +76,9 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
 }
 
 template <int K, int C>
-void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop,
+void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop, bool ilv,
                 uint64_t* lanes_run) {
-  const ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, pop.sorted);
+  const ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, pop.sorted, ilv);
   ht::NativeOp<K> op;
   for (int u = 0; u < (1 << K); ++u) op.perm[u] = pop.perm[u];
   op.active = pop.active;
@@ -101,14 +109,15 @@ extern "C" {
 // raw: host c128 tiled storage of nelems entries (2*nelems doubles), updated
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
-// ranges of the flattened work order (generic passes).  native: allow the
+// ranges of the flattened work order (generic passes).  ilv: the alternating
+// patch order (lane_block).  native: allow the
 // native pass for permutation-and-phase operations; *form (if not NULL)
 // receives the form used.  Returns 0 on success, 1 on invalid op, 2 on an
 // out-of-range access.  *lanes_run receives the number of lane bodies run.
 int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, const int* targets,
                      int r, const double* kraus, int heisenberg, int32_t* write_counts,
                      int32_t* read_counts, uint64_t* lanes_run, int order, int native,
-                     int* form, char* err, size_t errlen) {
+                     int ilv, int* form, char* err, size_t errlen) {
   const int m = tile_log2 < n ? tile_log2 : n;
   ht::PreparedOp op;
   if (ht::prepare_op(n, m, k, targets, r, kraus, heisenberg, &op, err, errlen, native) != 0)
@@ -119,7 +128,7 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   uint64_t lanes = 0;
 #define HT_CASE(K_, C_, F_)                                 \
   if (op.k == K_ && op.ncross == C_ && op.form == F_)       \
-    run<ht::conj_unroll(K_), K_, C_, F_>(mem, n, m, op, order, &lanes);
+    run<ht::conj_unroll(K_), K_, C_, F_>(mem, n, m, op, order, ilv != 0, &lanes);
   HT_CASE(1, 0, 0)
   HT_CASE(1, 0, 1)
   HT_CASE(1, 1, 0)
@@ -132,7 +141,7 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   HT_CASE(2, 2, 1)
 #undef HT_CASE
 #define HT_NATIVE(K_, C_) \
-  if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, &lanes);
+  if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, ilv != 0, &lanes);
   HT_NATIVE(1, 0)
   HT_NATIVE(1, 1)
   HT_NATIVE(2, 0)

@@ -25,8 +25,12 @@ struct LaunchTuning {
   int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
   int order = 0;            // 0: a wave walks a whole group; 1: waves share a group's patches
   int native = 1;           // 1: permutation-and-phase operations use the native pass
+  int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
 };
 LaunchTuning& tuning();
+// The patch order of a pass (alternating measured faster for both storage
+// types: +1 % for 16-byte entries, up to +10 % for 8-byte ones).
+inline bool use_interleave(int /*entry_bytes*/) { return tuning().interleave != 0; }
 
 // Enqueue one conjugation pass.  dtype 0: c128, 1: c64.  coef_dev is a device
 // buffer of >= 512 doubles that holds op.coef when the kernel reads its

@@ -129,7 +129,7 @@ HT_HD void native3_group_lane(const Mem& mem, const ConjGeom<3, C>& g, const Nat
   for (uint32_t job = 0; job < g.jobs; ++job) {
     const uint32_t b = job * 64u + lane;
     uint32_t pidx, qidx;
-    lane_block(b, g.F, g.s, pidx, qidx);
+    lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
     const uint32_t p = deposit_free<KI>(pidx, g.ipos);
     const uint32_t q = deposit_free<KI>(qidx, g.ipos);
     if (b >= nblk || (ng.diag && p < q)) continue;
@@ -172,7 +172,7 @@ HT_HD void native_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const Nati
     for (int j = 0; j < JU; ++j) {
       const uint32_t b = (job + j) * 64u + lane;
       uint32_t pidx, qidx;
-      lane_block(b, g.F, g.s, pidx, qidx);
+      lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
       bp[j] = deposit_free<KI>(pidx, g.ipos);
       bq[j] = deposit_free<KI>(qidx, g.ipos);
       on[j] = job + j < g.jobs && b < nblk && !(ng.diag && bp[j] < bq[j]);

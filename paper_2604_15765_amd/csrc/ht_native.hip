@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(256)
 template <typename T, int K, int C>
 static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const double* coef_dev,
                            int num_cu, hipStream_t s) {
-  const ConjGeom<K, C> g = make_geom<K, C>(n, m, pop.sorted);
+  const ConjGeom<K, C> g = make_geom<K, C>(n, m, pop.sorted, use_interleave((int)sizeof(T) * 2));
   NativeOp<K> op;
   for (int u = 0; u < (1 << K); ++u) op.perm[u] = pop.perm[u];
   op.active = pop.active;

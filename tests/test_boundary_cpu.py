@@ -170,7 +170,8 @@ def test_native_tuning_switch(ht):
 def test_tuning_validation(ht):
     ht.set_tuning("conj_wg_per_cu", 8)
     ht.set_tuning("conj_block_threads", 256)
-    for name, v in (("conj_wg_per_cu", 0), ("conj_block_threads", 100), ("nope", 1)):
+    ht.set_tuning("interleave", 1)
+    for name, v in (("conj_wg_per_cu", 0), ("conj_block_threads", 100), ("nope", 1), ("interleave", 2)):
         with pytest.raises(ht.HermError):
             ht.set_tuning(name, v)
 

@@ -35,14 +35,15 @@ def hc():
     vp = ctypes.c_void_p
     f.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp,
                   ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_int,
-                  ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, ctypes.c_size_t]
+                  ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, ctypes.c_size_t]
     f.restype = ctypes.c_int
     return f
 
 
-def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=False):
+def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=False, ilv=0):
     """Run one pass on the CPU.  native=0 keeps the generic forms (direct,
-    transfer); native=1 lets permutation-and-phase ops take the native pass."""
+    transfer); native=1 lets permutation-and-phase ops take the native pass;
+    ilv=1 the alternating patch order."""
     raw = np.ascontiguousarray(raw, dtype=np.complex128).copy()
     kraus = np.ascontiguousarray(kraus, dtype=np.complex128)
     t = np.ascontiguousarray(targets, dtype=np.int32)
@@ -51,7 +52,8 @@ def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=Fal
     form = ctypes.c_int(-1)
     err = ctypes.create_string_buffer(256)
     rc = f(raw.ctypes.data, raw.size, n, m, len(targets), t.ctypes.data, kraus.shape[0], kraus.ctypes.data,
-           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, native, ctypes.byref(form), err, 256)
+           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, native, ilv, ctypes.byref(form), err,
+           256)
     assert rc == 0, err.value.decode()
     if want_form:
         return raw, wc, form.value
@@ -70,7 +72,8 @@ def check(f, n, m, targets, kraus, heis, rng):
     H = synth.random_hermitian_dense(n, rng)
     raw = layout.encode(H, m)
     order = int(rng.integers(2))  # both work orders of the kernel
-    out, wc = emulate(f, raw, n, m, targets, kraus, heis, order)
+    ilv = int(rng.integers(2))    # both patch orders
+    out, wc = emulate(f, raw, n, m, targets, kraus, heis, order, ilv=ilv)
     assert np.all(wc == 1), f"write counts {np.unique(wc)} for n={n} m={m} t={targets}"
     got = layout.decode(out, n, m)
     ref = reference(H, kraus, targets, heis)
@@ -153,7 +156,8 @@ def check_native(f, n, m, targets, kraus, heis, rng):
     are written, once each."""
     H = synth.random_hermitian_dense(n, rng)
     raw = layout.encode(H, m)
-    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, native=1, want_form=True)
+    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, native=1, want_form=True,
+                            ilv=int(rng.integers(2)))
     changing = changing_entries(kraus, targets, heis)
     assert form == (2 if len(targets) == 3 or not changing.all() else (0 if kraus.shape[0] == 1 else 1)), \
         (targets, form)
@@ -237,5 +241,5 @@ def test_three_qubit_ops_need_the_native_form(hc):
     err = ctypes.create_string_buffer(256)
     lanes = ctypes.c_uint64()
     rc = hc(raw.ctypes.data, raw.size, n, m, 3, t.ctypes.data, 1, kraus.ctypes.data, 0, None, None,
-            ctypes.byref(lanes), 0, 1, None, err, 256)
+            ctypes.byref(lanes), 0, 1, 0, None, err, 256)
     assert rc == 1 and b"k = 3" in err.value
