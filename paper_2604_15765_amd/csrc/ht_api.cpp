@@ -429,8 +429,8 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src) {
 
 // A k = 3 operation outside the native form is valid input the library does
 // not implement; every other preparation failure is an invalid argument.
-static ht_status op_error(const char* msg) {
-  return std::strncmp(msg, "k = 3 is supported", 18) == 0 ? HT_EUNSUPPORTED : HT_EINVAL;
+static ht_status op_error(int prep_result) {
+  return prep_result == ht::kPrepUnsupported ? HT_EUNSUPPORTED : HT_EINVAL;
 }
 
 static ht_status apply(ht_herm* h, int k, const int* targets, int r, const double* mats,
@@ -440,9 +440,9 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
     return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   ht::PreparedOp op;
   char msg[256];
-  if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
-                     sizeof msg, ht::tuning().native) != 0)
-    return ht_fail(op_error(msg), "%s", msg);
+  const int pr = ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
+                                sizeof msg, ht::tuning().native);
+  if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
   return ht_launch_prepared(h, op);
 }
 
@@ -623,9 +623,9 @@ ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
     return ht_fail(HT_EINVAL, "unknown picture %d", (int)picture);
   ht::PreparedOp op;
   char msg[256];
-  if (ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg, sizeof msg,
-                     ht::tuning().native) != 0)
-    return ht_fail(op_error(msg), "%s", msg);
+  const int pr = ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg,
+                                sizeof msg, ht::tuning().native);
+  if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
   if (sorted_targets)
     for (int l = 0; l < op.k; ++l) sorted_targets[l] = op.sorted[l];
   if (ncross) *ncross = op.ncross;

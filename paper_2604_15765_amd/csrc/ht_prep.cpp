@@ -184,9 +184,11 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
     if (st < 0) return 1;
     if (st == 1) return 0;
   }
-  if (k == 3)
-    return fail("k = 3 is supported for permutation-and-phase operations only (one nonzero "
-                "per row of every Kraus operator, in the same column for all of them)");
+  if (k == 3) {
+    fail("k = 3 is supported for permutation-and-phase operations only (one nonzero "
+         "per row of every Kraus operator, in the same column for all of them)");
+    return kPrepUnsupported;
+  }
 
   if (r == 1) {
     out->form = 0;

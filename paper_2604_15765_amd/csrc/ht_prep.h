@@ -27,8 +27,12 @@ struct PreparedOp {
   double coef[2 * 256];
 };
 
+// prepare_op's result for a valid op outside what the kernels implement (a
+// k = 3 op that is not permutation-and-phase); other failures return 1.
+constexpr int kPrepUnsupported = 2;
+
 // Validate and prepare.  Returns 0 on success; otherwise writes a message to
-// err (errlen bytes) and returns nonzero.  m_eff is the effective tile
+// err (errlen bytes) and returns 1 (invalid argument) or kPrepUnsupported.  m_eff is the effective tile
 // exponent of the operator (min(tile_log2, n)).  allow_native: use form 2
 // when every Kraus operator has one nonzero entry per row, in the same
 // column for all of them (k = 3 is accepted only in that form).

@@ -8,6 +8,11 @@
 //                    cross-tile pass touches 4 or more tiles per group that
 //                    lie in different parts of the buffer), 16 loads of 16 B
 //                    in flight per lane, all loads of a step before its stores;
+//   tile_rmw<PAT>    in-place read-modify-write of 16 KiB tiles (32 x 32
+//                    16-byte entries), one tile per wave and step, 16 loads
+//                    per lane: PAT 0 contiguous 1 KiB per instruction, PAT 1
+//                    the conjugation pass's 8 x 8 lane patch (8 rows of
+//                    128 B at a 512-byte stride per instruction);
 //   read_stream      read-only; write_stream  write-only; copy_stream  copy.
 // Every kernel is a grid-stride loop over whole work items that lie inside
 // the buffer (items that would cross its end are not formed).
@@ -54,6 +59,34 @@ __global__ void __launch_bounds__(256) rmw_streams(u4* __restrict__ p, uint64_t 
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int i = 0; i < PER; ++i) st<NT>(p + s * slen + (it * PER + i) * 64 + lane, v[s * PER + i]);
+  }
+}
+
+template <int PAT>
+__global__ void __launch_bounds__(256) tile_rmw(u4* __restrict__ p, uint64_t ntiles, unsigned salt) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t t = wave; t < ntiles; t += nwaves) {
+    u4* tile = p + t * 1024;
+    uint32_t off[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if constexpr (PAT == 0)
+        off[i] = i * 64 + lane;
+      else
+        off[i] = ((i >> 2) * 8 + (lane >> 3)) * 32 + (i & 3) * 8 + (lane & 7);
+    }
+    u4 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(tile + off[i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      v[i].x ^= salt;
+      v[i].w += salt;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(v[i], tile + off[i]);
   }
 }
 
@@ -104,6 +137,19 @@ int htp_rmw(int nstreams, int nontemporal, void* buf, uint64_t n16, int grid, vo
   HTP_CASE(16)
 #undef HTP_CASE
   return (int)hipErrorInvalidValue;
+}
+
+// buf: ntiles tiles of 16 KiB.
+int htp_tile(int pattern, void* buf, uint64_t ntiles, int grid, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  u4* p = reinterpret_cast<u4*>(buf);
+  if (pattern == 0)
+    hipLaunchKernelGGL(tile_rmw<0>, dim3(grid), dim3(256), 0, s, p, ntiles, 7u);
+  else if (pattern == 1)
+    hipLaunchKernelGGL(tile_rmw<1>, dim3(grid), dim3(256), 0, s, p, ntiles, 7u);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
 }
 
 // out: grid * 256 unsigned

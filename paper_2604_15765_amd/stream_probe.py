@@ -6,7 +6,9 @@ Runs the kernels of csrc/ht_probe.hip (``_probe.so``, built with the
 library) on a buffer of the n = 16 complex128 operator's size and prints one
 JSON line: read-only, write-only and copy bandwidth, and in-place
 read-modify-write bandwidth for 1, 2, 4 and 16 concurrent far-apart streams,
-with and without nontemporal hints, each the best over a few grid sizes.
+with and without nontemporal hints, and in-place tile-by-tile streams of
+16 KiB tiles with contiguous and with 8 x 8-patch instructions, each the best
+over a few grid sizes.
 Bandwidth counts bytes read plus bytes written.
 """
 
@@ -26,6 +28,7 @@ def main():
     p = argparse.ArgumentParser()
     p.add_argument("--bytes", type=int, default=34376515584)
     p.add_argument("--reps", type=int, default=4)
+    p.add_argument("--summary", help="also write a text summary to this file")
     args = p.parse_args()
     lib = ctypes.CDLL(os.path.join(HERE, "_probe.so"))
     torch.cuda.set_device(0)
@@ -33,7 +36,7 @@ def main():
     n16 = nb // 16
     a = torch.zeros(nb, dtype=torch.uint8, device="cuda")
     b = torch.zeros(nb, dtype=torch.uint8, device="cuda")
-    grids = (1024, 2048, 4096)
+    grids = (1024, 2048, 4096, 8192)
     out = torch.empty(max(grids) * 256, dtype=torch.int32, device="cuda")
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     vp = ctypes.c_void_p
@@ -64,7 +67,38 @@ def main():
         for nt in (0, 1):
             r[f"rmw_{ns}streams_{'nt' if nt else 'plain'}_GBps"] = best(
                 lambda g, ns=ns, nt=nt: lib.htp_rmw(ns, nt, vp(a.data_ptr()), u64(n16), g, st), moved)
+    ntiles = nb // 16384
+    for pat, name in ((0, "contiguous"), (1, "patch8x8")):
+        r[f"tile_rmw_{name}_nt_GBps"] = best(
+            lambda g, pat=pat: lib.htp_tile(pat, vp(a.data_ptr()), u64(ntiles), g, st), 2 * ntiles * 16384)
     print(json.dumps(r), flush=True)
+    if args.summary:
+        write_summary(r, args.summary)
+
+
+def write_summary(r: dict, path: str) -> None:
+    lines = [
+        f"# HBM streaming ceilings on MI355X (gfx950), one {r['buffer_bytes']:,}-byte buffer "
+        "(the n = 16 c128 operator)",
+        "# command: python3 -m paper_2604_15765_amd.stream_probe --summary "
+        "profiles/hbm_stream_probe_n16_c128.txt   (kernels: paper_2604_15765_amd/csrc/ht_probe.hip)",
+        "# bandwidth = (bytes read + bytes written) / kernel time (torch events), best of grids "
+        "1024/2048/4096/8192 x 256 threads",
+        "# rmw_<S>streams: in-place read-modify-write of S far-apart regions in lockstep, 16 x 16 B loads "
+        "per lane in flight",
+        "#   (an intra-tile pass is one stream; a cross-tile pass groups 4 tiles from different parts of "
+        "the buffer, a two-tile-bit pass 16); nt = nontemporal loads and stores",
+        "# tile_rmw: one 16 KiB tile (32 x 32 entries) per wave and step, nontemporal; contiguous = 1 KiB "
+        "per load instruction,",
+        "#   patch8x8 = the conjugation pass's lane patch (8 rows x 128 B at a 512-byte stride per "
+        "instruction)",
+        "",
+    ]
+    for k, v in r.items():
+        if k.endswith("_GBps"):
+            lines.append(f"{k:34s} {v / 1000:6.3f} TB/s   ({100 * v / 8000:5.1f}% of the 8 TB/s spec)")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 if __name__ == "__main__":
