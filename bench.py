@@ -258,6 +258,8 @@ def main():
             "ops_per_step": nops / args.steps, "storage_bytes": h.nbytes, "tuning": tuning,
         },
         "hbm_GBps": nops * per_op_bytes / elapsed / 1e9,
+        # the paper's effective bandwidth: stored bytes / time per op (one direction)
+        "logical_GiBps": nops * h.nbytes / elapsed / 2 ** 30,
         "hbm_frac": nops * per_op_bytes / elapsed / 1e9 / HBM_PEAK_GBPS,
         "kernel_time_frac": kernel_ms * 1e-3 / elapsed,
         "roofline": {

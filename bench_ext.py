@@ -4,6 +4,7 @@
     python bench_ext.py serve     [--rates 10,100,1000] [--count 48]
     python bench_ext.py precision [--layers 4]
     python bench_ext.py native    [--reps 5]
+    python bench_ext.py paper     [--ns 6,8,10,12,14,16]
 
 Each prints one JSON line.  All inputs are seeded and synthetic (see synth/).
 
@@ -17,6 +18,10 @@ serve:     Poisson request streams (n log-uniform in 6..16, 10..300 mixed
            ops, c128/c64, half with a 64-term Pauli-sum readout) served by the
            continuous-batching server and by the one-at-a-time baseline on
            the same requests: circuits/s, p50/p99 latency, equal results.
+paper:     the paper's experiment shapes: one op type (depolarising, H, X,
+           Haar 1q, CNOT, Haar 2q) at every qubit position for n = 6..16
+           with the paper's logical bandwidth; the n = 8 circuit on the GPU
+           and the CPU oracle; the n = 14 sweep circuit per class.
 native:    permutation-and-phase gates (X, Z, T, dephasing, CNOT, CZ, SWAP,
            Toffoli, CCZ, Fredkin) at n = 16 with the native pass and with
            the generic pass: time per pass and algorithmic bytes moved.
@@ -346,6 +351,95 @@ def run_native(args):
                       "storage_bytes": h.nbytes, "results": results}), flush=True)
 
 
+# -------------------------------------------------------------------- paper
+
+def run_paper(args):
+    """The paper's own experiment shapes, on the GPU: one op type applied at
+    every qubit position for n = 6..16 (time per op, read+write GB/s, and
+    the paper's logical bandwidth = stored bytes / time per op, in GiB/s);
+    the n = 8 200-op circuit on the GPU and on the CPU oracle; the n = 14
+    sweep circuit with per-class rates and the oracle's per-op time."""
+    import torch
+    import oracle
+    import paper_2604_15765_amd as ht
+    import synth
+
+    torch.cuda.set_device(0)
+    rng = synth.make_rng(args.seed)
+    H1 = synth.named_gate("H")
+    X1 = synth.named_gate("X")
+    depol = synth.depolarising_kraus(0.1)
+    out = {"bench": "paper", "sweep": []}
+    for n in [int(x) for x in args.ns.split(",")]:
+        h = ht.Herm(n, 5).init_lowrank(torch.from_numpy(synth.ginibre_factor(n, 4, rng)).to("cuda"))
+        h.scale(1.0 / h.trace())
+        U1 = synth.haar_unitary(2, rng)
+        U2 = synth.haar_unitary(4, rng)
+        kinds = [("depolarising", 1, depol), ("H", 1, H1[None]), ("X", 1, X1[None]), ("haar1", 1, U1[None]),
+                 ("cnot", 2, synth.cnot_matrix()[None]), ("haar2", 2, U2[None])]
+        for name, k, mats in kinds:
+            positions = [[a] for a in range(n)] if k == 1 else [[a, a + 1] for a in range(n - 1)]
+            reps = max(2, min(50, int(2e9 / h.nbytes)))
+            for t in positions:  # warm every class
+                h.apply_channel(t, mats)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for t in positions:
+                for _ in range(reps):
+                    h.apply_channel(t, mats)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / (reps * len(positions))
+            row = {"n": n, "op": name, "us_per_op": dt * 1e6, "rw_GBps": 2 * h.nbytes / dt / 1e9,
+                   "logical_GiBps": h.nbytes / dt / 2 ** 30, "positions": len(positions)}
+            out["sweep"].append(row)
+            log(f"[paper] n={n} {name}: {row['us_per_op']:.1f} us/op, logical {row['logical_GiBps']:.0f} GiB/s")
+        h.close()
+        torch.cuda.empty_cache()
+
+    # n = 8, 200 ops: GPU (launch-bound) and the dense CPU oracle
+    G, ops = synth.circuit_plain_n8(seed=1234)
+    h = ht.Herm(8, 5).init_lowrank(torch.from_numpy(G).to("cuda"))
+    h.scale(1.0 / h.trace())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op in ops:
+        h.apply_op(op)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    rho = oracle.density_from_factor(G)
+    t0 = time.perf_counter()
+    ref = oracle.apply_ops(rho, ops)
+    t_cpu = time.perf_counter() - t0
+    out["n8_circuit"] = {"ops": len(ops), "gpu_s": t_gpu, "oracle_s": t_cpu,
+                         "rel_frobenius": float(np.linalg.norm(h.to_dense() - ref) / np.linalg.norm(ref))}
+    log(f"[paper] n=8 circuit: GPU {t_gpu * 1e3:.1f} ms, oracle {t_cpu:.1f} s")
+
+    # n = 14 sweep circuit: every class at every position
+    G, ops, _ = synth.circuit_sweep(n=14)
+    h = ht.Herm(14, 5).init_lowrank(torch.from_numpy(G).to("cuda"))
+    h.scale(1.0 / h.trace())
+    h.profile_reset()
+    h.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op in ops:
+        h.apply_op(op)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile_enable(False)
+    classes = {c: {"launches": v["launches"], "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+               for c, v in sorted(prof.items())}
+    rho = oracle.density_from_factor(G)
+    t0 = time.perf_counter()
+    rho = oracle.local_block_map(rho, ops[0].mats, ops[0].targets)
+    t_cpu = time.perf_counter() - t0
+    out["n14_sweep"] = {"ops": len(ops), "gate_conj_per_s": len(ops) / t_gpu, "classes": classes,
+                        "oracle_s_per_op": t_cpu, "oracle_ops_timed": 1}
+    log(f"[paper] n=14 sweep: {len(ops) / t_gpu:.0f} gate-conj/s on the GPU, oracle {t_cpu:.1f} s per op")
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- precision
 
 def run_precision(args):
@@ -442,9 +536,12 @@ def main():
     v = sub.add_parser("native")
     v.add_argument("--seed", type=int, default=1616)
     v.add_argument("--reps", type=int, default=5)
+    q = sub.add_parser("paper")
+    q.add_argument("--seed", type=int, default=530)
+    q.add_argument("--ns", default="6,8,10,12,14,16")
     args = p.parse_args()
     {"batched": run_batched, "serve": run_serve, "precision": run_precision,
-     "native": run_native}[args.cmd](args)
+     "native": run_native, "paper": run_paper}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -176,8 +176,11 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
  * qubit touches half of the storage, a CNOT three quarters).  Fixed entries
  * keep their bits; a phase product within 2^-50 of one on an entry the
  * permutation fixes counts as one.  k = 3 is supported for such matrices
- * only (HT_EUNSUPPORTED otherwise).  ht_set_tuning("native", 0) turns the
- * native pass off (k <= 2 then takes the generic forms). */
+ * only (HT_EUNSUPPORTED otherwise).  For k <= 2 the native pass is used on
+ * operators larger than the 256 MiB Infinity Cache, where the pass is bound
+ * by HBM (on cache-resident ones the generic pass is faster), and only when
+ * some entry stays in place.  ht_set_tuning("native", v): 0 off (k <= 2
+ * generic, k = 3 unsupported), 1 as described (default), 2 at every size. */
 ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,
                            ht_picture picture);
 
@@ -456,8 +459,9 @@ const char* ht_kernel_class_name(int idx);
  * nontemporal loads and stores when every store writes whole cache lines);
  * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
  * 0): 0 = each wave processes whole tile groups, 1 = the patches of a group
- * are spread over neighbouring waves.  "native" (0 or 1, default 1): the
- * native pass for permutation-and-phase operations.  "interleave" (0 or 1,
+ * are spread over neighbouring waves.  "native" (0, 1 or 2, default 1):
+ * the native pass for permutation-and-phase operations (see
+ * ht_apply_unitary).  "interleave" (0 or 1,
  * default 1): the order in which a lane walks its patches of a tile group,
  * 1 alternating column and row patches (whole cache lines of 8-byte entries
  * in mirrored tiles too).  HT_EINVAL for an unknown name or value. */
@@ -481,7 +485,9 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  *                      form 0, 2 * 16^k for form 1, 2 * 4^k + 2^k for form 2
  *                      (512 always suffice),
  * where the A_a are the caller's operators with their local bits reordered to
- * ascending target order and, in the Heisenberg picture, adjoined. */
+ * ascending target order and, in the Heisenberg picture, adjoined.  The
+ * native form is reported whenever the op has it (as for an operator beyond
+ * the cache), unless ht_set_tuning("native", 0). */
 ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
                         const double* kraus, ht_picture picture, int* sorted_targets,
                         int* ncross, int* form, double* coef);

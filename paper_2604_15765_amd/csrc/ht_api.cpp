@@ -441,7 +441,7 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
   ht::PreparedOp op;
   char msg[256];
   const int pr = ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
-                                sizeof msg, ht::tuning().native);
+                                sizeof msg, ht::native_policy(h->bytes));
   if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
   return ht_launch_prepared(h, op);
 }
@@ -602,7 +602,7 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     return HT_OK;
   }
   if (k == "native") {
-    if (value != 0 && value != 1) return ht_fail(HT_EINVAL, "native must be 0 or 1");
+    if (value < 0 || value > 2) return ht_fail(HT_EINVAL, "native must be 0, 1 or 2");
     ht::tuning().native = (int)value;
     return HT_OK;
   }
@@ -624,7 +624,7 @@ ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
   ht::PreparedOp op;
   char msg[256];
   const int pr = ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg,
-                                sizeof msg, ht::tuning().native);
+                                sizeof msg, ht::tuning().native != 0 ? 1 : 0);
   if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
   if (sorted_targets)
     for (int l = 0; l < op.k; ++l) sorted_targets[l] = op.sorted[l];

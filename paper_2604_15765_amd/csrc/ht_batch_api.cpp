@@ -41,7 +41,8 @@ int entry_ops(const ht_batch::Entry& e, int m_eff, int fuse_q, std::vector<Batch
     seq[i] = &f;
   }
   std::vector<PreparedOp> prepared;
-  if (fuse_ops(seq, fuse_q, e.h->n, m_eff, tuning().native, &prepared, err, errlen) != 0) return 1;
+  const size_t bytes = ht_storage_bytes(e.h->n, m_eff, e.h->dtype == 0 ? HT_C128 : HT_C64);
+  if (fuse_ops(seq, fuse_q, e.h->n, m_eff, native_policy(bytes), &prepared, err, errlen) != 0) return 1;
   for (const PreparedOp& op : prepared) append_batch_op(op, ops, coefs);
   return 0;
 }
@@ -61,7 +62,7 @@ ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, cons
   ht::PreparedOp op;
   char msg[256];
   if (ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
-                     sizeof msg, ht::tuning().native) != 0)
+                     sizeof msg, ht::native_policy(h->bytes)) != 0)
     return ht_fail(HT_EINVAL, "%s", msg);
   auto it = b->index.find(h);
   size_t e;

@@ -141,7 +141,7 @@ ht_status ht_circuit_apply(ht_circuit* c, ht_herm* h) {
     const ht::FusePass& p = c->passes[i];
     for (int l = 0; l < p.k; ++l)
       if (p.sorted[l] >= h->n) return ht_fail(HT_EINVAL, "pass %zu: qubit %d >= n", i, p.sorted[l]);
-    if (ht::fuse_prepare(p, c->seq, h->n, h->m, ht::tuning().native, &prepared[i], msg,
+    if (ht::fuse_prepare(p, c->seq, h->n, h->m, ht::native_policy(h->bytes), &prepared[i], msg,
                          sizeof msg) != 0)
       return ht_fail(HT_EINVAL, "pass %zu: %s", i, msg);
   }

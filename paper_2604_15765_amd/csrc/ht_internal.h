@@ -24,10 +24,20 @@ struct LaunchTuning {
   int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
   int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
   int order = 0;            // 0: a wave walks a whole group; 1: waves share a group's patches
-  int native = 1;           // 1: permutation-and-phase operations use the native pass
+  int native = 1;           // native pass: 0 never, 1 on operators beyond the cache, 2 always
   int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
 };
 LaunchTuning& tuning();
+// allow_native for prepare_op on an operator of `bytes` bytes: the native
+// pass only pays where the pass is bound by HBM (an operator larger than the
+// 256 MiB Infinity Cache: on cache-resident operators it measured up to 1.8x
+// slower than the generic pass); k = 3 always takes it (its only form).
+// (tuning "native": 0 never -- k = 3 then fails --, 1 by size, 2 always.)
+inline int native_policy(size_t bytes) {
+  if (tuning().native == 0) return 0;
+  if (tuning().native == 2) return 1;
+  return bytes > ((size_t)256 << 20) ? 1 : kNativeK3Only;
+}
 // The patch order of a pass (alternating measured faster for both storage
 // types: +1 % for 16-byte entries, up to +10 % for 8-byte ones).
 inline bool use_interleave(int /*entry_bytes*/) { return tuning().interleave != 0; }

@@ -154,7 +154,7 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
   }
 
   // permutation-and-phase form: one nonzero per row, same column in every A_a
-  bool mono = allow_native != 0;
+  bool mono = allow_native == 1 || (allow_native == kNativeK3Only && k == 3);
   int pm[8];
   for (int u = 0; u < D && mono; ++u) {
     pm[u] = -1;
@@ -233,7 +233,7 @@ int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S
     if (sorted[l] >= m_eff) ++out->ncross;
   }
   // native form if every row of S has one nonzero, at (p(u), p(v)) for one p
-  if (allow_native) {
+  if (allow_native == 1) {
     int pm[4] = {-1, -1, -1, -1};
     bool mono = true;
     cplx c[16];

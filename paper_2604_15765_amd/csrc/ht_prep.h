@@ -31,11 +31,15 @@ struct PreparedOp {
 // k = 3 op that is not permutation-and-phase); other failures return 1.
 constexpr int kPrepUnsupported = 2;
 
+// allow_native value that restricts the native form to k = 3.
+constexpr int kNativeK3Only = 2;
+
 // Validate and prepare.  Returns 0 on success; otherwise writes a message to
 // err (errlen bytes) and returns 1 (invalid argument) or kPrepUnsupported.  m_eff is the effective tile
-// exponent of the operator (min(tile_log2, n)).  allow_native: use form 2
-// when every Kraus operator has one nonzero entry per row, in the same
-// column for all of them (k = 3 is accepted only in that form).
+// exponent of the operator (min(tile_log2, n)).  allow_native: 1 = use form
+// 2 when every Kraus operator has one nonzero entry per row, in the same
+// column for all of them; kNativeK3Only = only for k = 3 (accepted only in
+// that form); 0 = never.
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
                int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native = 1);
 
@@ -43,7 +47,7 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
 // row-major, interleaved complex; w = S vec(h) with vec row-major over local
 // indices whose bit l belongs to sorted[l], ascending).  Uses the native
 // form when S has one nonzero per row at (p(u), p(v)) for one permutation p
-// and allow_native; else form 1.
+// and allow_native == 1; else form 1.
 int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S, int allow_native,
                      PreparedOp* out, char* err, size_t errlen);
 

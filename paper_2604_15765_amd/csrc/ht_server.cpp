@@ -535,7 +535,7 @@ ht_status ht_server_submit(ht_server* s, const ht_request* q, int64_t* id) {
     ht::PreparedOp op;
     char msg[256];
     if (ht::prepare_op(r->n, r->m, k, q->op_targets + 2 * i, q->op_r[i], q->op_mats + mat_off,
-                       q->picture == HT_HEISENBERG, &op, msg, sizeof msg, ht::tuning().native) != 0)
+                       q->picture == HT_HEISENBERG, &op, msg, sizeof msg, ht::native_policy(r->bytes)) != 0)
       return ht_fail(HT_EINVAL, "op %d: %s", i, msg);
     ht::FuseOp& f = fops[i];
     f.k = k;
@@ -553,7 +553,7 @@ ht_status ht_server_submit(ht_server* s, const ht_request* q, int64_t* id) {
     for (size_t i = 0; i < fops.size(); ++i) seq[i] = &fops[i];
     std::vector<ht::PreparedOp> prepared;
     char msg[256];
-    if (ht::fuse_ops(seq, s->cfg.fuse_qubits, r->n, r->m, ht::tuning().native, &prepared, msg,
+    if (ht::fuse_ops(seq, s->cfg.fuse_qubits, r->n, r->m, ht::native_policy(r->bytes), &prepared, msg,
                      sizeof msg) != 0)
       return ht_fail(HT_EINVAL, "fusing the request's ops: %s", msg);
     for (const ht::PreparedOp& op : prepared) ht::append_batch_op(op, r->ops, r->coefs);

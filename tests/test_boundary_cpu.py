@@ -164,7 +164,7 @@ def test_native_tuning_switch(ht):
     assert ht.prepare_op(4, 2, [1], synth.named_gate("X"))[2] == 0
     assert ht.prepare_op(4, 2, [1], synth.depolarising_kraus(0.1))[2] == 1
     with pytest.raises(ht.HermError):
-        ht.set_tuning("native", 2)
+        ht.set_tuning("native", 3)
 
 
 def test_tuning_validation(ht):

@@ -76,7 +76,11 @@ def test_fused_diagonal_groups_take_the_native_pass(ht):
     assert c.plan(0, 2) == 1
     h = ht.Herm(n, m).init_dense(H)
     h.profile_enable(True)
-    c.apply(h)
+    ht.set_tuning("native", 2)  # at every size (this operator is small)
+    try:
+        c.apply(h)
+    finally:
+        ht.set_tuning("native", 1)
     prof = h.profile_read()
     assert list(prof) == ["c128_k2_c1_native"], prof
     assert rel(h.to_dense(), oracle.apply_ops(H, ops)) <= TOL

@@ -24,8 +24,9 @@ def ht():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2604_15765_amd as ht
+    ht.set_tuning("native", 2)  # the native pass at every size (these operators are small)
+    yield ht
     ht.set_tuning("native", 1)
-    return ht
 
 
 def rel(a, b):
@@ -86,14 +87,14 @@ def test_native_agrees_with_generic_pass(ht):
                 for g in gate_set(k, rng):
                     H = synth.random_hermitian_dense(n, rng)
                     outs = []
-                    for native in (1, 0):
+                    for native in (2, 0):
                         ht.set_tuning("native", native)
                         h = ht.Herm(n, m).init_dense(H)
                         h.apply_channel(t, g)
                         outs.append(h.to_dense())
                     assert rel(outs[0], outs[1]) < 1e-14, (t, rel(outs[0], outs[1]))
     finally:
-        ht.set_tuning("native", 1)
+        ht.set_tuning("native", 2)
 
 
 def test_native_c64_one_rounding(ht):
