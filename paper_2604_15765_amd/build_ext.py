@@ -50,8 +50,8 @@ def _run(cmd, verbose):
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
-    lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-    _run([HIPCC, *lang, *COMMON, *DEVICE, "-c", path, "-o", obj], verbose)
+    # every source is HIP: the .cpp files use the HIP runtime API
+    _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj], verbose)
     return obj
 
 

@@ -59,7 +59,7 @@ __device__ void batch_native(S2<T>* base, int n, int m, const BatchOp& op,
   nop.c = coefs + op.coef_off;
   const DirectMem<T, 0> mem{base};
   for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves)
-    native_group_lane<1, K, C>(mem, g, native_group<K, C>(grp, g), nop, lane);
+    native_group_lane<1, K, C>(mem, g, native_group<C>(grp), nop, lane);
 }
 
 template <typename T>

@@ -72,7 +72,8 @@ ht_status add_op(ht_batch* b, ht_herm* h, int k, const int* targets, int r, cons
       b->num_cu = h->num_cu;
     }
     e = b->entries.size();
-    b->entries.push_back({h, {}, {}, {}, {}});
+    b->entries.emplace_back();
+    b->entries.back().h = h;
     b->index[h] = e;
   } else {
     e = it->second;

@@ -87,7 +87,7 @@ void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop, 
   ht::native_op_data(pop, data);
   op.c = data;
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
-    const ht::NativeGroup ng = ht::native_group<K, C>(grp, g);
+    const ht::NativeGroup ng = ht::native_group<C>(grp);
     for (uint32_t lane = 0; lane < 64; ++lane) {
       if constexpr (K == 3) {
         if (pop.chunk == 32)

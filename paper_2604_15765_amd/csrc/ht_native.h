@@ -47,8 +47,8 @@ struct NativeGroup {
   bool diag;
 };
 
-template <int K, int C>
-HT_HD NativeGroup native_group(uint64_t grp, const ConjGeom<K, C>& g) {
+template <int C>
+HT_HD NativeGroup native_group(uint64_t grp) {
   uint32_t Ti, Tj;
   tri_decode(grp, Ti, Tj);
   NativeGroup r;

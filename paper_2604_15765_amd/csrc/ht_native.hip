@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256)
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const DirectMem<T, MODE> mem{h};
   for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
-    const NativeGroup ng = native_group<K, C>(grp, g);
+    const NativeGroup ng = native_group<C>(grp);
     if constexpr (K == 3)
       native3_group_lane<C, CH>(mem, g, ng, op, lane);
     else
