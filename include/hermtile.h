@@ -419,7 +419,9 @@ ht_status ht_server_submit(ht_server* s, const ht_request* req, int64_t* id);
 /* Block until every submitted request has completed (HT_EDEVICE on timeout). */
 ht_status ht_server_wait_idle(ht_server* s, double timeout_s);
 /* Move up to max completed requests out of the server: id, status (HT_OK or
- * the failure), readout value and the times (seconds on the server's
+ * the failure: HT_ENOMEM when the device cannot allocate the request's
+ * operator, HT_EDEVICE when a launch failed; either way only that request
+ * fails and the server keeps serving), readout value and the times (seconds on the server's
  * monotonic clock) of submission, admission and completion.  Any output
  * array may be NULL.  *count receives the number written. */
 ht_status ht_server_poll(ht_server* s, int64_t max, int64_t* ids, int* status, double* values,

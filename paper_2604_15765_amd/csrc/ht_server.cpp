@@ -128,13 +128,19 @@ void set_error(ht_server* s, const std::string& msg) {
   if (s->error.empty()) s->error = msg;
 }
 
-// An operator buffer of exactly `bytes` within the budget, or nullptr.
-void* take_buffer(ht_server* s, size_t bytes) {
+// Outcome of asking for an operator buffer.
+enum class Take { kOk, kWait, kNoMemory };
+
+// An operator buffer of exactly `bytes` within the budget: kWait when the
+// budget is taken (memory frees up as requests finish), kNoMemory when the
+// device itself cannot provide it even after the pool is given back.
+Take take_buffer(ht_server* s, size_t bytes, void** out) {
+  *out = nullptr;
   auto it = s->pool.find(bytes);
   if (it != s->pool.end()) {
-    void* p = it->second;
+    *out = it->second;
     s->pool.erase(it);
-    return p;
+    return Take::kOk;
   }
   while (s->allocated + bytes > s->cfg.budget_bytes && !s->pool.empty()) {
     auto big = std::prev(s->pool.end());  // release the largest pooled buffer
@@ -142,11 +148,23 @@ void* take_buffer(ht_server* s, size_t bytes) {
     s->allocated -= big->first;
     s->pool.erase(big);
   }
-  if (s->allocated + bytes > s->cfg.budget_bytes) return nullptr;
+  if (s->allocated + bytes > s->cfg.budget_bytes) return Take::kWait;
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();  // clear the allocation error
+    for (auto& kv : s->pool) {
+      (void)hipFree(kv.second);
+      s->allocated -= kv.first;
+    }
+    s->pool.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return Take::kNoMemory;
+    }
+  }
   s->allocated += bytes;
-  return p;
+  *out = p;
+  return Take::kOk;
 }
 
 void give_buffer(ht_server* s, void* p, size_t bytes) { s->pool.emplace(bytes, p); }
@@ -246,16 +264,34 @@ void fail_request(ht_server* s, std::unique_ptr<Req>& rp, hipError_t e) {
 
 // Admit the request at the front of `pending` if a slot and its memory are
 // available (false: it has to wait).  A request whose initialisation cannot
-// be enqueued fails and is reported; the call still returns true.
+// be enqueued fails and is reported; the call still returns true.  A request
+// whose buffers the device cannot allocate fails with HT_ENOMEM unless the
+// memory of the resident requests, once they finish, would make room.
 bool admit_front(ht_server* s, std::deque<std::unique_ptr<Req>>& pending) {
   if (s->free_slots.empty()) return false;
   Req* r = pending.front().get();
-  void* buf = take_buffer(s, r->bytes);
-  if (!buf) return false;
-  void* gbuf = take_buffer(s, r->gbytes);
-  if (!gbuf) {
-    give_buffer(s, buf, r->bytes);
-    return false;
+  void* buf = nullptr;
+  void* gbuf = nullptr;
+  Take t = take_buffer(s, r->bytes, &buf);
+  if (t == Take::kOk) {
+    t = take_buffer(s, r->gbytes, &gbuf);
+    if (t != Take::kOk) give_buffer(s, buf, r->bytes);
+  }
+  if (t == Take::kWait) return false;
+  if (t == Take::kNoMemory) {
+    // Wait while the resident requests could free enough; fail otherwise.
+    size_t held = 0, free_b = 0, total_b = 0;
+    for (const auto& a : s->active) held += a->bytes + a->gbytes;
+    if (!s->active.empty() && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+        free_b + held >= r->bytes + r->gbytes)
+      return false;
+    std::unique_ptr<Req> rp = std::move(pending.front());
+    pending.pop_front();
+    rp->t_admit = s->now();
+    rp->status = HT_ENOMEM;
+    set_error(s, "request failed: the device cannot hold its operator");
+    finish(s, rp);
+    return true;
   }
   std::unique_ptr<Req> rp = std::move(pending.front());
   pending.pop_front();

@@ -120,3 +120,31 @@ def test_server_with_fusion(ht):
             if r["n"] <= 9:
                 want = _oracle_value(r)
                 assert abs(v - want) <= 1e-12 * max(1.0, abs(want)), (r["n"], v, want)
+
+
+def test_server_fails_only_the_request_the_device_cannot_hold(ht):
+    """An n = 18 complex128 request (about 550 GB, more than the device holds)
+    within a 1 TiB budget: it fails with HT_ENOMEM, alone, whether other
+    requests are resident or not, and the requests around it complete."""
+    reqs = _requests(83, 6, [4, 6, 9])
+    cfg = dict(batch_max_qubits=5, medium_max_qubits=7)
+    want, _ = _serve(ht, reqs, **cfg)
+    rng = synth.make_rng(84)
+    n_big = 18
+    assert ht.storage_bytes(n_big, 5, "c128") > torch.cuda.get_device_properties(0).total_memory
+    big = synth.ginibre_factor(n_big, 1, rng)
+    srv = ht.Server(budget_bytes=1 << 40, **cfg)
+    ids = [srv.submit(r["n"], r["G"], r["ops"], r["pauli"], r["dtype"]) for r in reqs[:3]]
+    bad = [srv.submit(n_big, big, [])]  # while the first ones are resident
+    ids += [srv.submit(r["n"], r["G"], r["ops"], r["pauli"], r["dtype"]) for r in reqs[3:]]
+    srv.wait_idle(300)
+    bad.append(srv.submit(n_big, big, []))  # with nothing else resident
+    ok = srv.submit(reqs[0]["n"], reqs[0]["G"], reqs[0]["ops"], reqs[0]["pauli"], reqs[0]["dtype"])
+    srv.wait_idle(300)
+    res = {d["id"]: d for d in srv.poll()}
+    assert "cannot hold" in srv.last_error()
+    srv.close()
+    assert [res[i]["status"] for i in bad] == [2, 2]  # HT_ENOMEM
+    assert [res[i]["status"] for i in ids + [ok]] == [0] * (len(ids) + 1)
+    assert [res[i]["value"] for i in ids] == want
+    assert res[ok]["value"] == want[0]
