@@ -157,7 +157,9 @@ ht_status ht_herm_get_entries(const ht_herm* h, int64_t count, const int64_t* ro
  * Synchronises. */
 ht_status ht_herm_read_raw(const ht_herm* h, size_t offset, size_t nbytes, void* out);
 
-/* dst = src (same n, tile edge and dtype). */
+/* dst = src (same n, tile edge and dtype).  Enqueued on dst's stream after
+ * src's stream (if different) has been synchronised; src must not be
+ * modified until dst's stream has passed the copy. */
 ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
 
 /* ------------------------------------------------------------- hot path -- */
@@ -466,7 +468,8 @@ const char* ht_kernel_class_name(int idx);
  * ht_apply_unitary).  "interleave" (0 or 1,
  * default 1): the order in which a lane walks its patches of a tile group,
  * 1 alternating column and row patches (whole cache lines of 8-byte entries
- * in mirrored tiles too).  HT_EINVAL for an unknown name or value. */
+ * in mirrored tiles too).  HT_EINVAL for an unknown name or value.  Set it
+ * while no other thread enqueues work (a server's scheduler thread reads it). */
 ht_status ht_set_tuning(const char* name, int64_t value);
 
 /* Pure host function (no GPU): the per-op preparation the library performs

@@ -207,6 +207,8 @@ class Herm:
         with torch.cuda.device(self.device):
             self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            if self.stream != torch.cuda.current_stream(self.device):
+                self.buffer.record_stream(self.stream)  # freed only after the stream's work
             h = ctypes.c_void_p()
             _check(lib.ht_herm_create(self.n, tile_log2, _DTYPES[dtype], ctypes.c_void_p(self.buffer.data_ptr()),
                                       nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
@@ -216,9 +218,11 @@ class Herm:
 
     # lifetime ----------------------------------------------------------
     def close(self) -> None:
+        """Destroy the handle (after its stream has drained) and release the storage."""
         if getattr(self, "_h", None):
             _check(lib.ht_herm_destroy(self._h))
             self._h = None
+            self.buffer = None
 
     def __del__(self):
         try:
@@ -239,6 +243,7 @@ class Herm:
     def set_stream(self, stream: torch.cuda.Stream) -> None:
         _check(lib.ht_herm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
         self.stream = stream
+        self.buffer.record_stream(stream)
 
     def synchronize(self) -> None:
         _check(lib.ht_herm_synchronize(self._h))

@@ -130,18 +130,27 @@ ht_status ht_launch_prepared(ht_herm* h, const ht::PreparedOp& op) {
     HT_HIP(ht::launch_upload(h->coef_dev, data, nd, h->stream));
   }
   hipEvent_t a = nullptr, b = nullptr;
+  // on a failure the events go back to the pool
+  auto fail = [&](hipError_t e, const char* what) {
+    if (a) h->pool.push_back(a);
+    if (b) h->pool.push_back(b);
+    return ht_fail(HT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  };
   if (h->prof) {
     a = take_event(h);
     b = take_event(h);
-    if (!a || !b) return ht_fail(HT_EDEVICE, "could not create profiling events");
-    HT_HIP(hipEventRecord(a, h->stream));
+    if (!a || !b) return fail(hipErrorOutOfMemory, "could not create profiling events");
+    const hipError_t e = hipEventRecord(a, h->stream);
+    if (e != hipSuccess) return fail(e, "hipEventRecord");
   }
-  if (op.form == 2)
-    HT_HIP(ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
-  else
-    HT_HIP(ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream));
+  const hipError_t e =
+      op.form == 2
+          ? ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream)
+          : ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream);
+  if (e != hipSuccess) return fail(e, "conjugation pass launch");
   if (h->prof) {
-    HT_HIP(hipEventRecord(b, h->stream));
+    const hipError_t eb = hipEventRecord(b, h->stream);
+    if (eb != hipSuccess) return fail(eb, "hipEventRecord");
     const int cls = h->dtype * ht::kClassesPerDtype + ht::conj_class(op.k, op.ncross, op.form);
     // algorithmic bytes: every stored entry read and written once, or for the
     // native pass the changing fraction of them

@@ -63,6 +63,7 @@ struct Req {
   bool large = false;    // lane > 0: runs plain passes on its slot's stream
   int chunks_in_flight = 0;  // large path: chunks enqueued and not yet seen complete (<= 2)
   int chunk_ev = 0;          // event slot the next chunk records
+  bool failed = false;       // its batch round could not be enqueued
 };
 
 // Per-slot resources, allocated once at server creation at their largest size
@@ -256,9 +257,13 @@ void finish(ht_server* s, std::unique_ptr<Req>& rp) {
   s->cv.notify_all();
 }
 
+// Fail a request after its enqueued work has drained (its buffers go back to
+// the pool and may be handed to the next request at once).
 void fail_request(ht_server* s, std::unique_ptr<Req>& rp, hipError_t e) {
   rp->status = HT_EDEVICE;
   set_error(s, std::string("request failed: ") + hipGetErrorString(e));
+  if (rp->slot >= 0) (void)hipStreamSynchronize(s->slots[rp->slot].stream);
+  if (rp->lane == 0) (void)hipStreamSynchronize(s->batch_stream);
   finish(s, rp);
 }
 
@@ -454,7 +459,19 @@ void scheduler(ht_server* s) {
             r->state = READOUT;
           }
         }
-        if (e != hipSuccess) set_error(s, std::string("batch round failed: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+          // the round's ops may not have run: every request in it fails
+          set_error(s, std::string("batch round failed: ") + hipGetErrorString(e));
+          for (Req* r : batch_ready) r->failed = true;
+          for (size_t i = 0; i < s->active.size();) {
+            if (s->active[i]->failed) {
+              fail_request(s, s->active[i], e);
+              s->active.erase(s->active.begin() + i);
+            } else {
+              ++i;
+            }
+          }
+        }
         s->next_runner ^= 1;
         progressed = true;
       }
