@@ -461,9 +461,10 @@ const char* ht_kernel_class_name(int idx);
  * of the grid-stride grid.  "conj_block_threads" (64, 128 or 256, default
  * 256): workgroup size.  "conj_mem_mode" (-1..3, default -1 = automatic:
  * nontemporal loads and stores when every store writes whole cache lines);
- * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (0 or 1, default
- * 0): 0 = each wave processes whole tile groups, 1 = the patches of a group
- * are spread over neighbouring waves.  "native" (0, 1 or 2, default 1):
+ * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (-1, 0 or 1,
+ * default -1): 0 = each wave processes whole tile groups, 1 = the patches of
+ * a group are spread over neighbouring waves, -1 = 1 when there are fewer
+ * groups than the grid has waves, else 0.  "native" (0, 1 or 2, default 1):
  * the native pass for permutation-and-phase operations (see
  * ht_apply_unitary).  "interleave" (0 or 1,
  * default 1): the order in which a lane walks its patches of a tile group,

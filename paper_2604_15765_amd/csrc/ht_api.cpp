@@ -601,7 +601,7 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     return HT_OK;
   }
   if (k == "conj_order") {
-    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "conj_order must be 0 or 1");
+    if (value < -1 || value > 1) return ht_fail(HT_EINVAL, "conj_order must be -1, 0 or 1");
     ht::tuning().order = (int)value;
     return HT_OK;
   }

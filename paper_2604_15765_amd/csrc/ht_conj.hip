@@ -69,9 +69,13 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   const int threads = tuning().block_threads;
   const uint64_t waves_per_wg = (uint64_t)threads / 64;
   const uint64_t steps = (g.jobs + conj_unroll(K, (int)sizeof(T) * 2) - 1) / conj_unroll(K, (int)sizeof(T) * 2);
-  const uint64_t items = tuning().order == 0 ? g.ngroups : g.ngroups * steps;
-  uint64_t wgs = (items + waves_per_wg - 1) / waves_per_wg;
   const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
+  // automatic order: split groups over waves when whole groups would leave
+  // the grid's waves idle (small operators, few large cross-tile groups)
+  int order = tuning().order;
+  if (order < 0) order = g.ngroups < cap * waves_per_wg ? 1 : 0;
+  const uint64_t items = order == 0 ? g.ngroups : g.ngroups * steps;
+  uint64_t wgs = (items + waves_per_wg - 1) / waves_per_wg;
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
@@ -86,19 +90,19 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   switch (mode) {
     case 1:
       hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 1>), dim3((unsigned)wgs), dim3(threads), 0, s,
-                         hp, g, cf, coef_dev, tuning().order);
+                         hp, g, cf, coef_dev, order);
       break;
     case 2:
       hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 2>), dim3((unsigned)wgs), dim3(threads), 0, s,
-                         hp, g, cf, coef_dev, tuning().order);
+                         hp, g, cf, coef_dev, order);
       break;
     case 3:
       hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 3>), dim3((unsigned)wgs), dim3(threads), 0, s,
-                         hp, g, cf, coef_dev, tuning().order);
+                         hp, g, cf, coef_dev, order);
       break;
     default:
       hipLaunchKernelGGL((conj_kernel<T, K, C, FORM, 0>), dim3((unsigned)wgs), dim3(threads), 0, s,
-                         hp, g, cf, coef_dev, tuning().order);
+                         hp, g, cf, coef_dev, order);
   }
   return hipGetLastError();
 }

@@ -76,7 +76,7 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
 }
 
 template <int K, int C>
-void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop, bool ilv,
+void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop, int order, bool ilv,
                 uint64_t* lanes_run) {
   const ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, pop.sorted, ilv);
   ht::NativeOp<K> op;
@@ -88,15 +88,22 @@ void run_native(const CheckedMem& mem, int n, int m, const ht::PreparedOp& pop, 
   op.c = data;
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
     const ht::NativeGroup ng = ht::native_group<C>(grp);
+    constexpr int JU = ht::native_unroll(K);
     for (uint32_t lane = 0; lane < 64; ++lane) {
-      if constexpr (K == 3) {
-        if (pop.chunk == 32)
-          ht::native3_group_lane<C, 32>(mem, g, ng, op, lane);
-        else
-          ht::native3_group_lane<C, 16>(mem, g, ng, op, lane);
+      // order 1: the per-step job ranges of the flattened work order
+      const uint32_t step = order == 0 ? 0xffffffffu : (uint32_t)JU;
+      for (uint32_t j0 = 0; j0 < g.jobs; j0 += step) {
+        const uint32_t j1 = order == 0 ? 0xffffffffu : j0 + JU;
+        if constexpr (K == 3) {
+          if (pop.chunk == 32)
+            ht::native3_group_lane<C, 32>(mem, g, ng, op, lane, j0, j1);
+          else
+            ht::native3_group_lane<C, 16>(mem, g, ng, op, lane, j0, j1);
+        } else {
+          ht::native_group_lane<JU, K, C>(mem, g, ng, op, lane, j0, j1);
+        }
+        if (order == 0) break;
       }
-      else
-        ht::native_group_lane<ht::native_unroll(K), K, C>(mem, g, ng, op, lane);
       ++*lanes_run;
     }
   }
@@ -109,7 +116,7 @@ extern "C" {
 // raw: host c128 tiled storage of nelems entries (2*nelems doubles), updated
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
-// ranges of the flattened work order (generic passes).  ilv: the alternating
+// ranges of the flattened work order.  ilv: the alternating
 // patch order (lane_block).  native: allow the
 // native pass for permutation-and-phase operations; *form (if not NULL)
 // receives the form used.  Returns 0 on success, 1 on invalid op, 2 on an
@@ -141,7 +148,7 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   HT_CASE(2, 2, 1)
 #undef HT_CASE
 #define HT_NATIVE(K_, C_) \
-  if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, ilv != 0, &lanes);
+  if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, order, ilv != 0, &lanes);
   HT_NATIVE(1, 0)
   HT_NATIVE(1, 1)
   HT_NATIVE(2, 0)

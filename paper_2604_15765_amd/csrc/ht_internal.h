@@ -23,7 +23,8 @@ struct LaunchTuning {
   int block_threads = 256;  // 4 waves per workgroup
   int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
   int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
-  int order = 0;            // 0: a wave walks a whole group; 1: waves share a group's patches
+  int order = -1;           // 0: a wave walks a whole group; 1: waves share a group's
+                            // patches; -1: 1 when there are fewer groups than the grid's waves
   int native = 1;           // native pass: 0 never, 1 on operators beyond the cache, 2 always
   int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
 };

@@ -38,7 +38,7 @@ struct NativeOp {
 
 
 // Blocks in flight per lane: 4 (k = 1, 16 entries) or 1 (k = 2, 16 entries);
-// k = 3 walks its block in chunks of 16 or 32 entries.
+// k = 3 walks its block in chunks of 16 or 32 entries (one block per step).
 constexpr int native_unroll(int K) { return K == 1 ? 4 : 1; }
 
 // The group: reduced tile indices Ti >= Tj.
@@ -121,12 +121,16 @@ HT_HD void native_store(const Mem& mem, const ConjGeom<K, C>& g, const NativeGro
 // chunk closed under the permutation and under transposition, so loading
 // all of a chunk's sources before writing it is safe in place, also where an
 // entry and its transpose share storage).
+// Jobs [job_begin, job_end) of the group (all by default), as in
+// conj_group_lane.
 template <int C, int CH, typename Mem>
 HT_HD void native3_group_lane(const Mem& mem, const ConjGeom<3, C>& g, const NativeGroup& ng,
-                              const NativeOp<3>& op, uint32_t lane) {
+                              const NativeOp<3>& op, uint32_t lane, uint32_t job_begin = 0,
+                              uint32_t job_end = 0xffffffffu) {
   constexpr int KI = 3 - C;
   const uint32_t nblk = 1u << (2 * g.F);
-  for (uint32_t job = 0; job < g.jobs; ++job) {
+  if (job_end > g.jobs) job_end = g.jobs;
+  for (uint32_t job = job_begin; job < job_end; ++job) {
     const uint32_t b = job * 64u + lane;
     uint32_t pidx, qidx;
     lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
@@ -160,11 +164,13 @@ HT_HD void native3_group_lane(const Mem& mem, const ConjGeom<3, C>& g, const Nat
 // a block's entries lie in the same block, and blocks are disjoint.
 template <int JU, int K, int C, typename Mem>
 HT_HD void native_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const NativeGroup& ng,
-                             const NativeOp<K>& op, uint32_t lane) {
+                             const NativeOp<K>& op, uint32_t lane, uint32_t job_begin = 0,
+                             uint32_t job_end = 0xffffffffu) {
   constexpr int D = 1 << K;
   constexpr int KI = K - C;
   const uint32_t nblk = 1u << (2 * g.F);
-  for (uint32_t job = 0; job < g.jobs; job += JU) {
+  if (job_end > g.jobs) job_end = g.jobs;
+  for (uint32_t job = job_begin; job < job_end; job += JU) {
     uint32_t bp[JU], bq[JU];
     bool on[JU];
     cd x[JU][D * D];
@@ -175,7 +181,7 @@ HT_HD void native_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const Nati
       lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
       bp[j] = deposit_free<KI>(pidx, g.ipos);
       bq[j] = deposit_free<KI>(qidx, g.ipos);
-      on[j] = job + j < g.jobs && b < nblk && !(ng.diag && bp[j] < bq[j]);
+      on[j] = job + j < job_end && b < nblk && !(ng.diag && bp[j] < bq[j]);
       if (on[j]) {
 #pragma unroll
         for (int u = 0; u < D; ++u)

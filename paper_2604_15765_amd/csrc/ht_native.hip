@@ -11,7 +11,10 @@
 
 namespace ht {
 
-template <typename T, int K, int C, int MODE, int CH>
+// ORDER is a template parameter (not a run-time switch as in the
+// conjugation pass): with both walks in one body the k = 2 intra-tile kernel
+// needs one register more and loses a wave per SIMD.
+template <typename T, int K, int C, int MODE, int CH, int ORDER>
 __global__ void __launch_bounds__(256)
     native_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, NativeOp<K> op) {
   const uint32_t lane = threadIdx.x & 63u;
@@ -19,12 +22,29 @@ __global__ void __launch_bounds__(256)
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const DirectMem<T, MODE> mem{h};
-  for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
-    const NativeGroup ng = native_group<C>(grp);
-    if constexpr (K == 3)
-      native3_group_lane<C, CH>(mem, g, ng, op, lane);
-    else
-      native_group_lane<native_unroll(K), K, C>(mem, g, ng, op, lane);
+  constexpr int JU = native_unroll(K);
+  if constexpr (ORDER == 0) {
+    // one wave walks all patches of a group
+    for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
+      const NativeGroup ng = native_group<C>(grp);
+      if constexpr (K == 3)
+        native3_group_lane<C, CH>(mem, g, ng, op, lane);
+      else
+        native_group_lane<JU, K, C>(mem, g, ng, op, lane);
+    }
+  } else {
+    // (group, step of JU patches) items: neighbouring waves sweep one group
+    const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
+    const int sl = 31 - __builtin_clz(steps);
+    const uint64_t items = g.ngroups << sl;
+    for (uint64_t it = wave; it < items; it += nwaves) {
+      const NativeGroup ng = native_group<C>(it >> sl);
+      const uint32_t j0 = (uint32_t)(it & (steps - 1)) * JU;
+      if constexpr (K == 3)
+        native3_group_lane<C, CH>(mem, g, ng, op, lane, j0, j0 + JU);
+      else
+        native_group_lane<JU, K, C>(mem, g, ng, op, lane, j0, j0 + JU);
+    }
   }
 }
 
@@ -39,8 +59,14 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const
   op.c = coef_dev;
   const int threads = tuning().block_threads;
   const uint64_t waves_per_wg = (uint64_t)threads / 64;
-  uint64_t wgs = (g.ngroups + waves_per_wg - 1) / waves_per_wg;
   const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
+  // work order as for the conjugation pass
+  int order = tuning().order;
+  if (order < 0) order = g.ngroups < cap * waves_per_wg ? 1 : 0;
+  constexpr int JU = native_unroll(K);
+  const uint64_t steps = (g.jobs + JU - 1) / JU;
+  const uint64_t items = order == 0 ? g.ngroups : g.ngroups * steps;
+  uint64_t wgs = (items + waves_per_wg - 1) / waves_per_wg;
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
@@ -51,19 +77,29 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const
     constexpr int KI = K - C;
     mode = (sizeof(T) == 8 && (KI == 0 || g.ipos[0] >= 3)) ? 3 : 0;
   }
-  if (K == 3 && pop.chunk == 32) {  // orbits longer than 16 entries (rare permutations)
-    if (mode == 3)
-      hipLaunchKernelGGL((native_kernel<T, K, C, 3, 32>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
-    else
-      hipLaunchKernelGGL((native_kernel<T, K, C, 0, 32>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
+  const dim3 grid((unsigned)wgs), block(threads);
+  if constexpr (K == 3) {
+    if (pop.chunk == 32) {  // orbits longer than 16 entries (rare permutations)
+      if (order == 1)
+        hipLaunchKernelGGL((native_kernel<T, K, C, 0, 32, 1>), grid, block, 0, s, hp, g, op);
+      else if (mode == 3)
+        hipLaunchKernelGGL((native_kernel<T, K, C, 3, 32, 0>), grid, block, 0, s, hp, g, op);
+      else
+        hipLaunchKernelGGL((native_kernel<T, K, C, 0, 32, 0>), grid, block, 0, s, hp, g, op);
+      return hipGetLastError();
+    }
+  }
+  if (order == 1) {
+    // few groups: an operator of at most a few hundred MB, plain hints
+    hipLaunchKernelGGL((native_kernel<T, K, C, 0, 16, 1>), grid, block, 0, s, hp, g, op);
   } else if (mode == 3) {
-    hipLaunchKernelGGL((native_kernel<T, K, C, 3, 16>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
+    hipLaunchKernelGGL((native_kernel<T, K, C, 3, 16, 0>), grid, block, 0, s, hp, g, op);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((native_kernel<T, K, C, 1, 16>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
+    hipLaunchKernelGGL((native_kernel<T, K, C, 1, 16, 0>), grid, block, 0, s, hp, g, op);
   } else if (mode == 2) {
-    hipLaunchKernelGGL((native_kernel<T, K, C, 2, 16>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
+    hipLaunchKernelGGL((native_kernel<T, K, C, 2, 16, 0>), grid, block, 0, s, hp, g, op);
   } else {
-    hipLaunchKernelGGL((native_kernel<T, K, C, 0, 16>), dim3((unsigned)wgs), dim3(threads), 0, s, hp, g, op);
+    hipLaunchKernelGGL((native_kernel<T, K, C, 0, 16, 0>), grid, block, 0, s, hp, g, op);
   }
   return hipGetLastError();
 }

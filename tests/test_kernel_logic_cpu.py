@@ -150,13 +150,14 @@ def test_pauli_x_twice_is_bitwise_identity(hc, native):
 
 # ------------------------------------------------------ native pass (form 2)
 
-def check_native(f, n, m, targets, kraus, heis, rng):
+def check_native(f, n, m, targets, kraus, heis, rng, order=None):
     """Native pass: form 2 unless k <= 2 and every entry changes (then the
     generic pass, which moves the same bytes); exactly the changing entries
-    are written, once each."""
+    are written, once each, in either work order of the kernel."""
     H = synth.random_hermitian_dense(n, rng)
     raw = layout.encode(H, m)
-    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, native=1, want_form=True,
+    order = int(rng.integers(2)) if order is None else order
+    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, order=order, native=1, want_form=True,
                             ilv=int(rng.integers(2)))
     changing = changing_entries(kraus, targets, heis)
     assert form == (2 if len(targets) == 3 or not changing.all() else (0 if kraus.shape[0] == 1 else 1)), \
@@ -218,6 +219,20 @@ def test_native_three_qubit_gates(hc, m):
             for g in gates:
                 check_native(hc, n, m, list(t), g, bool(rng.integers(2)), rng)
             check_native(hc, n, m, list(t), synth.random_monomial(3, rng)[None], bool(rng.integers(2)), rng)
+
+
+def test_native_split_work_order_at_the_benchmark_tile_edge(hc):
+    """Tile edge 32, where a group has several steps of patches: the work
+    order that spreads a group's steps over waves writes the same entries
+    once each, for k = 1, 2, 3 and every count of tile-selecting targets."""
+    rng = synth.make_rng(940)
+    n, m = 7, 5
+    cases = [([2], synth.named_gate("X")), ([6], synth.named_gate("T")), ([5], synth.named_gate("Y")),
+             ([1, 3], synth.cnot_matrix()), ([6, 2], synth.cnot_matrix()), ([5, 6], synth.permutation_gate("CZ")),
+             ([0, 4, 2], synth.permutation_gate("TOFFOLI")), ([6, 1, 3], synth.permutation_gate("FREDKIN")),
+             ([5, 6, 0], synth.random_monomial(3, rng)), ([4, 5, 6], synth.permutation_gate("CCZ"))]
+    for t, g in cases:
+        check_native(hc, n, m, t, g[None], bool(rng.integers(2)), rng, order=1)
 
 
 def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
