@@ -20,8 +20,10 @@ serve:     Poisson request streams (n log-uniform in 6..16, 10..300 mixed
            the same requests: circuits/s, p50/p99 latency, equal results.
 paper:     the paper's experiment shapes: one op type (depolarising, H, X,
            Haar 1q, CNOT, Haar 2q) at every qubit position for n = 6..16
-           with the paper's logical bandwidth; the n = 8 circuit on the GPU
-           and the CPU oracle; the n = 14 sweep circuit per class.
+           with the paper's logical bandwidth (median and 95 % CI of repeated
+           intervals); the n = 8 circuit on the GPU and the CPU oracle; the
+           n = 14 sweep circuit per class, in both pictures (duality), and
+           its whole evolved state against the CPU oracle.
 native:    permutation-and-phase gates (X, Z, T, dephasing, CNOT, CZ, SWAP,
            Toffoli, CCZ, Fredkin) at n = 16 with the native pass and with
            the generic pass: time per pass and algorithmic bytes moved.
@@ -36,6 +38,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -193,17 +196,26 @@ def run_batched(args):
     log(f"[batched] fused: {npasses} passes for {nops} ops; max deviation from unfused {fused_dev:.2e}")
 
     # oracle on a stratified sample: the first `per_n` operators of each n
+    # (32 per n: 256 operators), timed on the host as the CPU rate
     worst = 0.0
     checked = 0
+    oracle_s = 0.0
+    oracle_ops = 0
     seen = {}
     for h, ht_, (n, G, ops) in zip(batched, tuned, work):
         if seen.get(n, 0) >= args.per_n:
             continue
         seen[n] = seen.get(n, 0) + 1
+        t0 = time.perf_counter()
         ref = oracle.apply_ops_local(oracle.density_from_factor(G), ops)
+        oracle_s += time.perf_counter() - t0
+        oracle_ops += len(ops)
         for x in (h, ht_):
             worst = max(worst, float(np.linalg.norm(x.to_dense() - ref) / np.linalg.norm(ref)))
         checked += 1
+        if checked % 16 == 0:
+            log(f"[batched] oracle: {checked} operators checked, {oracle_s:.1f} s so far")
+    log(f"[batched] oracle: {checked} operators, {oracle_ops} ops in {oracle_s:.1f} s, max error {worst:.2e}")
     out = {
         "bench": "batched",
         "operators": args.count, "ops": nops,
@@ -222,7 +234,10 @@ def run_batched(args):
                   "passes": npasses, "max_rel_frobenius_vs_unfused_n_le_8": fused_dev},
         "speedup_vs_plain": t_plain / t_batch, "speedup_vs_graph": t_graph / t_batch,
         "bitwise_equal": {"graph": same_graph, "batched": same_batch, "tuned_vs_plain": same_tuned},
-        "oracle_check": {"operators": checked, "max_rel_frobenius": worst, "tolerance": 1e-12},
+        "oracle_check": {"operators": checked, "max_rel_frobenius": worst, "tolerance": 1e-12,
+                         "oracle_s": oracle_s, "oracle_circuits_per_s": checked / oracle_s,
+                         "oracle_gate_conj_per_s": oracle_ops / oracle_s,
+                         "host_threads": len(os.sched_getaffinity(0))},
         "state": "Ginibre factor of rank min(2^n, 64), normalised",
     }
     print(json.dumps(out), flush=True)
@@ -458,8 +473,11 @@ def run_paper(args):
                          "rel_frobenius": float(np.linalg.norm(h.to_dense() - ref) / np.linalg.norm(ref))}
     log(f"[paper] n=8 circuit: GPU {t_gpu * 1e3:.1f} ms, oracle {t_cpu:.1f} s")
 
-    # n = 14 sweep circuit: every class at every position
-    G, ops, _ = synth.circuit_sweep(n=14)
+    # n = 14 sweep circuit: every class at every position.  Schroedinger on
+    # the state, Heisenberg on a 64-term Pauli sum through the adjoint circuit
+    # in reverse order; duality tr(O Phi(rho)) = tr(Phi*(O) rho) on the GPU,
+    # and the whole evolved state against the oracle's local-block form
+    G, ops, (codes, coeffs) = synth.circuit_sweep(n=14)
     h = ht.Herm(14, 5).init_lowrank(torch.from_numpy(G).to("cuda"))
     h.scale(1.0 / h.trace())
     h.profile_reset()
@@ -474,13 +492,44 @@ def run_paper(args):
     h.profile_enable(False)
     classes = {c: {"launches": v["launches"], "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                for c, v in sorted(prof.items())}
-    rho = oracle.density_from_factor(G)
+    O = ht.Herm(14, 5).init_pauli_sum(codes, coeffs)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rho = oracle.local_block_map(rho, ops[0].mats, ops[0].targets)
-    t_cpu = time.perf_counter() - t0
-    out["n14_sweep"] = {"ops": len(ops), "gate_conj_per_s": len(ops) / t_gpu, "classes": classes,
-                        "oracle_s_per_op": t_cpu, "oracle_ops_timed": 1}
-    log(f"[paper] n=14 sweep: {len(ops) / t_gpu:.0f} gate-conj/s on the GPU, oracle {t_cpu:.1f} s per op")
+    for op in reversed(ops):
+        O.apply_op(op, ht.HEISENBERG)
+    torch.cuda.synchronize()
+    t_heis = time.perf_counter() - t0
+    rho0 = ht.Herm(14, 5).init_lowrank(torch.from_numpy(G).to("cuda"))
+    rho0.scale(1.0 / rho0.trace())
+    e_s = h.expectation_pauli_sum(codes, coeffs)
+    e_h = O.expectation(rho0)
+    O.close()
+    rho0.close()
+    res = {"ops": len(ops), "gate_conj_per_s": len(ops) / t_gpu, "classes": classes,
+           "heisenberg_gate_conj_per_s": len(ops) / t_heis,
+           "expectation_schroedinger": e_s, "expectation_heisenberg": e_h,
+           "duality_abs_diff": abs(e_s - e_h)}
+    log(f"[paper] n=14 sweep: {len(ops) / t_gpu:.0f} gate-conj/s (Heisenberg {len(ops) / t_heis:.0f}); "
+        f"duality |{e_s:.6e} - {e_h:.6e}| = {abs(e_s - e_h):.1e}")
+    if args.n14_oracle:
+        got = h.to_dense()
+        h.close()
+        torch.cuda.empty_cache()
+        rho = oracle.density_from_factor(G)
+        t_cpu = 0.0
+        for i, op in enumerate(ops):
+            t0 = time.perf_counter()
+            rho = oracle.local_block_map(rho, op.mats, op.targets)
+            t_cpu += time.perf_counter() - t0
+            if (i + 1) % 8 == 0:
+                log(f"[paper] n=14 oracle: {i + 1}/{len(ops)} ops, {t_cpu:.0f} s")
+        res["oracle_s_per_op"] = t_cpu / len(ops)
+        res["oracle_ops_timed"] = len(ops)
+        res["rel_frobenius_vs_oracle"] = float(np.linalg.norm(got - rho) / np.linalg.norm(rho))
+        res["host_threads"] = len(os.sched_getaffinity(0))
+        log(f"[paper] n=14 vs oracle (whole state, {len(ops)} ops): {res['rel_frobenius_vs_oracle']:.2e}, "
+            f"oracle {res['oracle_s_per_op']:.2f} s per op")
+    out["n14_sweep"] = res
     print(json.dumps(out), flush=True)
 
 
@@ -560,7 +609,7 @@ def main():
     b.add_argument("--tile-log2", type=int, default=5)
     b.add_argument("--threads", type=int, default=256)
     b.add_argument("--wg-per-cu", type=int, default=2)
-    b.add_argument("--per-n", type=int, default=2, help="operators per n checked against the oracle")
+    b.add_argument("--per-n", type=int, default=32, help="operators per n checked against the oracle")
     b.add_argument("--tune-sample", type=int, default=512, help="operators the autotuner times")
     s = sub.add_parser("serve")
     s.add_argument("--rates", default="10,100,1000")
@@ -584,6 +633,8 @@ def main():
     q.add_argument("--seed", type=int, default=530)
     q.add_argument("--ns", default="6,8,10,12,14,16")
     q.add_argument("--reps", type=int, default=10, help="timing intervals per (n, op, position)")
+    q.add_argument("--no-n14-oracle", dest="n14_oracle", action="store_false",
+                   help="skip the whole-state oracle run of the n = 14 sweep circuit (minutes on the host)")
     args = p.parse_args()
     {"batched": run_batched, "serve": run_serve, "precision": run_precision,
      "native": run_native, "paper": run_paper}[args.cmd](args)
