@@ -341,6 +341,33 @@ def test_largest_operator(ht):
     torch.cuda.empty_cache()
 
 
+def test_largest_c64_operator(ht):
+    """The largest operator one MI355X holds: n = 18 in complex64 storage
+    (262144 x 262144, 274.9 GB of tiles, element offsets beyond 2^34), with a
+    tile-selecting unitary, a channel across the farthest tiles and a native
+    CNOT, each within one float rounding on sampled blocks, plus the trace."""
+    n = 18
+    torch.cuda.empty_cache()
+    need = ht.storage_bytes(n, 5, "c64")
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (6 << 30):
+        pytest.skip(f"needs about {(need >> 30) + 6} GiB of free device memory")
+    rng = synth.make_rng(918)
+    h = ht.Herm(n, 5, "c64")
+    assert h.nbytes == need == 274_911_461_376
+    h.init_lowrank(synth.ginibre_factor(n, 8, rng))
+    h.scale(1.0 / h.trace())
+    ops = [synth.random_ops.unitary_op([n - 1], synth.haar_unitary(2, rng)),
+           synth.random_ops.channel_op([n - 2, 0], synth.random_kraus_set(2, 2, rng)),
+           synth.random_ops.unitary_op([n - 1, n - 3], synth.cnot_matrix())]
+    for i, op in enumerate(ops):
+        e = _sampled_op_check(h, op, i % 2 if op.kind == "unitary" else 0, n, rng, nblocks=800)
+        assert e <= 2 * C64_EPS, (op.targets, e)
+    assert abs(h.trace() - 1.0) < 1e-6
+    h.close()
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------- complex64
 
 C64_EPS = 2.0 ** -24  # unit roundoff of float32 (round to nearest)
