@@ -180,9 +180,13 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
  * permutation fixes counts as one.  k = 3 is supported for such matrices
  * only (HT_EUNSUPPORTED otherwise).  For k <= 2 the native pass is used on
  * operators larger than the 256 MiB Infinity Cache, where the pass is bound
- * by HBM (on cache-resident ones the generic pass is faster), and only when
- * some entry stays in place.  ht_set_tuning("native", v): 0 off (k <= 2
- * generic, k = 3 unsupported), 1 as described (default), 2 at every size. */
+ * by HBM (on cache-resident ones the generic pass is faster), when some
+ * entry stays in place, and when the fixed entries fill whole 128-byte
+ * lines, i.e. whether an entry changes is decided by targets at bit 3 or
+ * above (for diagonal matrices also bit 2, or any bits when at most 3/8 of
+ * the entries change); otherwise the generic pass, measured faster there.
+ * ht_set_tuning("native", v): 0 off (k <= 2 generic, k = 3 unsupported), 1
+ * as described (default), 2 whenever the matrix allows it, at every size. */
 ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,
                            ht_picture picture);
 

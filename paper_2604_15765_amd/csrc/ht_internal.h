@@ -32,12 +32,14 @@ LaunchTuning& tuning();
 // allow_native for prepare_op on an operator of `bytes` bytes: the native
 // pass only pays where the pass is bound by HBM (an operator larger than the
 // 256 MiB Infinity Cache: on cache-resident operators it measured up to 1.8x
-// slower than the generic pass); k = 3 always takes it (its only form).
-// (tuning "native": 0 never -- k = 3 then fails --, 1 by size, 2 always.)
+// slower than the generic pass), and there only where the op's fixed entries
+// fill whole cache lines (kNativeWherePays); k = 3 always takes it (its only
+// form).  (tuning "native": 0 never -- k = 3 then fails --, 1 where it pays,
+// 2 always.)
 inline int native_policy(size_t bytes) {
   if (tuning().native == 0) return 0;
   if (tuning().native == 2) return 1;
-  return bytes > ((size_t)256 << 20) ? 1 : kNativeK3Only;
+  return bytes > ((size_t)256 << 20) ? kNativeWherePays : kNativeK3Only;
 }
 // The patch order of a pass (alternating measured faster for both storage
 // types: +1 % for 16-byte entries, up to +10 % for 8-byte ones).

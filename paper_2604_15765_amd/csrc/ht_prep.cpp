@@ -36,12 +36,41 @@ using cplx = std::complex<double>;
 // most 4 units in the last place instead of the product's own rounding.
 constexpr double kUnitSnap = 1.0 / 1125899906842624.0;  // 2^-50
 
+// Whether the native pass of a k <= 2 op moves fewer bytes than the generic
+// pass in practice.  It skips the fixed entries, but HBM moves whole 128-byte
+// lines (eight 16-byte entries, columns differing in bits 0..2): where a
+// target below bit 3 decides whether a column's entry changes, every line
+// still holds changing entries.  Measured on n = 16 operators (tile edge
+// 32), the native pass was then 1-9 % slower for permutations (CNOT with a
+// low control, SWAP) and for diagonal ops changing half the entries at bits
+// 0, 1 (Z, T, dephasing), and faster for diagonal ops at bit 2 (+8 %) or
+// changing at most 3/8 of the entries (CZ: +5-11 %), and for every op whose
+// deciding targets lie at bit 3 or above (+22 % to 2.6x).
+static bool native_pays(int k, int m_eff, const int* sorted, const int* pm, uint64_t active) {
+  const int D = 1 << k;
+  int lowest = 64;  // lowest intra target whose column bit decides whether an entry changes
+  for (int l = 0; l < k; ++l) {
+    if (sorted[l] >= m_eff) continue;  // selects tiles: no effect inside a line
+    bool decides = false;
+    for (int u = 0; u < D && !decides; ++u)
+      for (int v = 0; v < D && !decides; ++v)
+        decides = ((active >> (u * D + v)) & 1) != ((active >> (u * D + (v ^ (1 << l)))) & 1);
+    if (decides && sorted[l] < lowest) lowest = sorted[l];
+  }
+  if (lowest >= 3) return true;
+  bool diagonal = true;
+  for (int u = 0; u < D; ++u) diagonal = diagonal && pm[u] == u;
+  const int changing = __builtin_popcountll(active);
+  return diagonal && (lowest == 2 || 8 * changing <= 3 * D * D);
+}
+
 // Fill the native form from the permutation pm and coefficients c (2^k x 2^k,
 // w[u][v] = c[u][v] h[pm[u]][pm[v]]).  Returns 1 when the native form is
 // used, 0 when the op should take a generic form instead (k <= 2 and every
-// entry changes: the native pass would move the same bytes), -1 on error.
-static int native_form(int k, const int* pm, const cplx* c_in, PreparedOp* out, char* err,
-                       size_t errlen) {
+// entry changes: the native pass would move the same bytes; or, under
+// kNativeWherePays, the native pass does not pay), -1 on error.
+static int native_form(int k, const int* pm, const cplx* c_in, int allow_native, int m_eff,
+                       const int* sorted, PreparedOp* out, char* err, size_t errlen) {
   const int D = 1 << k;
   out->form = 2;
   out->active = 0;
@@ -60,6 +89,8 @@ static int native_form(int k, const int* pm, const cplx* c_in, PreparedOp* out, 
   // (it then moves fewer bytes); an op that changes every entry (X, Y, ...)
   // keeps the generic pass, which is exact for permutations too.
   if (k <= 2 && out->active == (((uint64_t)1 << (D * D)) - 1)) return 0;
+  if (k <= 2 && allow_native == kNativeWherePays && !native_pays(k, m_eff, sorted, pm, out->active))
+    return 0;
   // k = 3: chunks of whole orbits (first fit, largest orbits first); a cycle
   // of (u, v) -> (p(u), p(v)) is at most the lcm of two cycle lengths of p
   // (<= 15), an orbit at most two cycles
@@ -154,7 +185,8 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
   }
 
   // permutation-and-phase form: one nonzero per row, same column in every A_a
-  bool mono = allow_native == 1 || (allow_native == kNativeK3Only && k == 3);
+  bool mono = allow_native == 1 || allow_native == kNativeWherePays ||
+              (allow_native == kNativeK3Only && k == 3);
   int pm[8];
   for (int u = 0; u < D && mono; ++u) {
     pm[u] = -1;
@@ -180,7 +212,7 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
         c[u * D + v] = 0.0;
         for (int a = 0; a < r; ++a) c[u * D + v] += A[a][u * D + pm[u]] * std::conj(A[a][v * D + pm[v]]);
       }
-    const int st = native_form(k, pm, c, out, err, errlen);
+    const int st = native_form(k, pm, c, allow_native, m_eff, out->sorted, out, err, errlen);
     if (st < 0) return 1;
     if (st == 1) return 0;
   }
@@ -233,7 +265,7 @@ int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S
     if (sorted[l] >= m_eff) ++out->ncross;
   }
   // native form if every row of S has one nonzero, at (p(u), p(v)) for one p
-  if (allow_native == 1) {
+  if (allow_native == 1 || allow_native == kNativeWherePays) {
     int pm[4] = {-1, -1, -1, -1};
     bool mono = true;
     cplx c[16];
@@ -260,7 +292,7 @@ int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S
       mono = seen == (1 << D) - 1;
     }
     if (mono) {
-      const int st = native_form(k, pm, c, out, err, errlen);
+      const int st = native_form(k, pm, c, allow_native, m_eff, sorted, out, err, errlen);
       if (st < 0) return 1;
       if (st == 1) return 0;
     }

@@ -33,13 +33,18 @@ constexpr int kPrepUnsupported = 2;
 
 // allow_native value that restricts the native form to k = 3.
 constexpr int kNativeK3Only = 2;
+// allow_native value for operators whose passes stream from HBM: the native
+// form for k = 3, and for k <= 2 only where it moved fewer bytes in
+// measurement (see native_pays in ht_prep.cpp).
+constexpr int kNativeWherePays = 3;
 
 // Validate and prepare.  Returns 0 on success; otherwise writes a message to
 // err (errlen bytes) and returns 1 (invalid argument) or kPrepUnsupported.  m_eff is the effective tile
 // exponent of the operator (min(tile_log2, n)).  allow_native: 1 = use form
 // 2 when every Kraus operator has one nonzero entry per row, in the same
-// column for all of them; kNativeK3Only = only for k = 3 (accepted only in
-// that form); 0 = never.
+// column for all of them; kNativeWherePays = the same for k = 3, and for
+// k <= 2 only where the native pass pays; kNativeK3Only = only for k = 3
+// (accepted only in that form); 0 = never.
 int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double* kraus,
                int heisenberg, PreparedOp* out, char* err, size_t errlen, int allow_native = 1);
 
@@ -47,7 +52,8 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
 // row-major, interleaved complex; w = S vec(h) with vec row-major over local
 // indices whose bit l belongs to sorted[l], ascending).  Uses the native
 // form when S has one nonzero per row at (p(u), p(v)) for one permutation p
-// and allow_native == 1; else form 1.
+// and allow_native is 1 (or kNativeWherePays and the native pass pays); else
+// form 1.
 int prepare_transfer(int n, int m_eff, int k, const int* sorted, const double* S, int allow_native,
                      PreparedOp* out, char* err, size_t errlen);
 

@@ -235,6 +235,32 @@ def test_native_split_work_order_at_the_benchmark_tile_edge(hc):
         check_native(hc, n, m, t, g[None], bool(rng.integers(2)), rng, order=1)
 
 
+def test_native_policy_for_operators_beyond_the_cache(hc):
+    """Under the size-based policy (native = 3 here) a k <= 2 op takes the
+    native pass only where its fixed entries fill whole 128-byte lines:
+    whether an entry changes is decided by targets at bit 3 or above (for
+    diagonal ops also bit 2, or any bits when at most 3/8 of the entries
+    change); k = 3 always.  Tile edge 32, so bits 5 and 6 select tiles."""
+    rng = synth.make_rng(945)
+    n, m = 7, 5
+    Z, X = synth.named_gate("Z")[None], synth.named_gate("X")[None]
+    cnot, cz, swap = (synth.cnot_matrix()[None], synth.permutation_gate("CZ")[None],
+                      synth.permutation_gate("SWAP")[None])
+    expect = [([0], Z, False), ([1], Z, False), ([2], Z, True), ([3], Z, True), ([6], Z, True),
+              ([2], synth.dephasing_kraus(0.2), True), ([0], synth.dephasing_kraus(0.2), False),
+              ([0, 1], cnot, False), ([1, 2], cnot, False), ([2, 3], cnot, False), ([3, 4], cnot, True),
+              ([2, 6], cnot, False), ([6, 2], cnot, True), ([5, 6], cnot, True), ([0, 4], cnot, False),
+              ([0, 1], cz, True), ([1, 2], cz, True), ([2, 6], cz, True),
+              ([0, 1], swap, False), ([2, 3], swap, False), ([3, 4], swap, True), ([2, 6], swap, False),
+              ([0], X, False), ([0, 1, 2], synth.permutation_gate("TOFFOLI")[None], True)]
+    raw = layout.encode(synth.random_hermitian_dense(n, rng), m)
+    for t, g, native in expect:
+        out, wc, form = emulate(hc, raw, n, m, t, g, False, native=3, want_form=True)
+        assert (form == 2) == native, (t, g.shape, form)
+        ref = reference(layout.decode(raw, n, m), g, t, False)
+        assert rel(layout.decode(out, n, m), ref) < 1e-13
+
+
 def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
     rng = synth.make_rng(950)
     n, m = 4, 2
