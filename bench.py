@@ -17,6 +17,9 @@ the most time, against MI355X's 8 TB/s; ``cpu_baseline`` = the CPU oracle
 ``fused`` = the same steps from the same state with each layer run as a
 fused circuit (ops grouped into 2-qubit passes), see ``fused_run()``.
 ``value`` is the op-by-op figure: one pass per op, as the method defines.
+``serving`` = the metric's served half: circuits/s and p50/p99 latency of a
+Poisson request stream under continuous batching (and with each request's
+ops fused) against the plain one-at-a-time baseline, see ``serve_run()``.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16] [--tile-log2 5]
 """
@@ -46,6 +49,9 @@ def parse():
     p.add_argument("--seed", type=int, default=1616)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fused", action="store_true", help="skip the fused-circuit run of the same steps")
+    p.add_argument("--no-serve", action="store_true", help="skip the served-requests run")
+    p.add_argument("--serve-count", type=int, default=48, help="requests of the served-requests run")
+    p.add_argument("--serve-rate", type=float, default=1000.0, help="Poisson arrival rate (/s) of that run")
     p.add_argument("--cpu-sample-n", type=int, default=12,
                    help="qubits of the dense sub-operator the CPU oracle is timed on")
     p.add_argument("--tune", action="append", default=[], metavar="NAME=VALUE",
@@ -146,6 +152,52 @@ def fused_run(ht, h, G, layers, args, codes, coeffs, tr_plain, ev_plain) -> dict
         "pauli_expectation_diff_vs_op_by_op": abs(ev - ev_plain),
         "note": "each layer as one ht_circuit: neighbouring ops composed in FP64 into passes on at most "
                 "2 qubits (ops on disjoint qubits reordered), one streaming pass per group",
+    }
+
+
+def serve_run(ht, count: int, rate: float, seed: int) -> dict:
+    """The served half of the metric: a Poisson stream of `count` requests
+    (n log-uniform in 6..16, 10..300 mixed ops, c128/c64, half with a 64-term
+    Pauli-sum readout; the stream `bench_ext.py serve` sweeps) served by the
+    continuous-batching server and by the plain one-at-a-time baseline on the
+    same requests: circuits/s and p50/p99 latency (arrival to result)."""
+    import synth
+    reqs = synth.serving_requests(count, rate, seed=seed)
+
+    def stream(**cfg):
+        srv = ht.Server(**cfg)
+        t_start = srv.now()
+        ids = []
+        for r in reqs:
+            while srv.now() - t_start < r["arrival"]:
+                time.sleep(min(0.001, max(0.0, r["arrival"] - (srv.now() - t_start))))
+            ids.append(srv.submit(r["n"], r["G"], r["ops"], r["pauli"], r["dtype"]))
+        srv.wait_idle(1800)
+        res = {d["id"]: d for d in srv.poll()}
+        srv.close()
+        recs = [res[i] for i in ids]
+        lat = np.array([d["t_done"] - d["t_submit"] for d in recs])
+        span = max(d["t_done"] for d in recs) - min(d["t_submit"] for d in recs)
+        return ({"circuits_per_s": len(recs) / span, "p50_s": float(np.percentile(lat, 50)),
+                 "p99_s": float(np.percentile(lat, 99)),
+                 "failed": sum(1 for d in recs if d["status"] != 0)}, [d["value"] for d in recs])
+
+    cont, v_cont = stream()
+    log(f"[bench] served (continuous batching): {cont}")
+    fused, v_fused = stream(fuse_qubits=2)
+    log(f"[bench] served (continuous batching, each request's ops fused into 2-qubit passes): {fused}")
+    fifo, v_fifo = stream(fifo=1)
+    log(f"[bench] served (one at a time): {fifo}")
+    return {
+        "requests": count, "rate_per_s": rate, "ops": sum(len(r["ops"]) for r in reqs),
+        "unit": "circuits/s", "continuous": cont, "continuous_fused": fused, "plain_fifo": fifo,
+        "throughput_ratio": cont["circuits_per_s"] / fifo["circuits_per_s"],
+        "p99_ratio": fifo["p99_s"] / cont["p99_s"],
+        "p50_ratio": fifo["p50_s"] / cont["p50_s"],
+        "fused_throughput_ratio": fused["circuits_per_s"] / fifo["circuits_per_s"],
+        "fused_p99_ratio": fifo["p99_s"] / fused["p99_s"],
+        "results_bitwise_equal": v_cont == v_fifo,
+        "fused_max_rel_dev": max(abs(a - b) / max(1.0, abs(b)) for a, b in zip(v_fused, v_fifo)),
     }
 
 
@@ -279,6 +331,10 @@ def main():
     }
     if not args.no_fused:
         out["fused"] = fused_run(ht, h, G, layers, args, codes, coeffs, tr, ev)
+    if not args.no_serve:
+        h.close()
+        torch.cuda.empty_cache()
+        out["serving"] = serve_run(ht, args.serve_count, args.serve_rate, args.seed)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, min(args.cpu_sample_n, n), args.seed)
