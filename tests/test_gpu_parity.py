@@ -140,6 +140,41 @@ def test_complex_nonsymmetric_channels(ht):
             _check_op(ht, 8, m, [a], kr, 0, rng)
 
 
+def test_work_orders_give_bitwise_equal_results(ht):
+    """Whole groups per wave (order 0) and group steps spread over waves
+    (order 1, the default below one group per wave) update the same blocks
+    with the same arithmetic: bitwise equal storage, generic and native
+    passes, every class."""
+    rng = synth.make_rng(470)
+    n = 9
+    H = synth.random_hermitian_dense(n, rng)
+    ops = []
+    for _ in range(30):
+        k = int(rng.integers(1, 3))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        c = rng.random()
+        mats = (synth.haar_unitary(1 << k, rng)[None] if c < 0.4 else
+                synth.random_kraus_set(k, 2, rng) if c < 0.7 else
+                (synth.cnot_matrix() if k == 2 else synth.named_gate("T"))[None])
+        ops.append((t, mats))
+    ops.append(([1, 7, 4], synth.permutation_gate("TOFFOLI")[None]))
+    ht.set_tuning("native", 2)
+    try:
+        for m in (3, 5):
+            out = []
+            for order in (0, 1):
+                ht.set_tuning("conj_order", order)
+                h = make(ht, n, m, H)
+                for t, mats in ops:
+                    h.apply_channel(t, mats)
+                out.append(h.raw_entries())
+                h.close()
+            assert np.array_equal(out[0], out[1]), m
+    finally:
+        ht.set_tuning("conj_order", -1)
+        ht.set_tuning("native", 1)
+
+
 def test_native_gate_exactness(ht):
     """X twice is the identity bitwise; CNOT leaves the control-0 quarter
     bitwise unchanged; S leaves entries with equal target bits unchanged."""
