@@ -177,15 +177,17 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src);
  * touch the entries the gate fixes (a diagonal gate on a tile-selecting
  * qubit touches half of the storage, a CNOT three quarters).  Fixed entries
  * keep their bits; a phase product within 2^-50 of one on an entry the
- * permutation fixes counts as one.  k = 3 is supported for such matrices
- * only (HT_EUNSUPPORTED otherwise).  For k <= 2 the native pass is used on
+ * permutation fixes counts as one.  Other k = 3 operations take a Kraus-form
+ * pass (8 lanes per block of 64 entries, an LDS exchange between the left
+ * and right products): every entry read and written once, 128 FP64 flops
+ * per entry per Kraus operator.  For k <= 2 the native pass is used on
  * operators larger than the 256 MiB Infinity Cache, where the pass is bound
  * by HBM (on cache-resident ones the generic pass is faster), when some
  * entry stays in place, and when the fixed entries fill whole 128-byte
  * lines, i.e. whether an entry changes is decided by targets at bit 3 or
  * above (for diagonal matrices also bit 2, or any bits when at most 3/8 of
  * the entries change); otherwise the generic pass, measured faster there.
- * ht_set_tuning("native", v): 0 off (k <= 2 generic, k = 3 unsupported), 1
+ * ht_set_tuning("native", v): 0 off (k <= 2 generic, k = 3 Kraus form), 1
  * as described (default), 2 whenever the matrix allows it, at every size. */
 ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* U,
                            ht_picture picture);
@@ -491,9 +493,11 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  *                      2: native permutation-and-phase form (coef holds the
  *                      2^k x 2^k coefficients c, then 2^k doubles p(0..2^k-1);
  *                      block entry w[u][v] = c[u][v] h[p(u)][p(v)]),
+ *                      3: k = 3 Kraus form (coef holds the r 8 x 8 operators
+ *                      A_a one after the other; w = sum_a A_a h A_a^dagger),
  *   coef               interleaved complex, row-major: 2 * 4^k doubles for
- *                      form 0, 2 * 16^k for form 1, 2 * 4^k + 2^k for form 2
- *                      (512 always suffice),
+ *                      form 0, 2 * 16^k for form 1, 2 * 4^k + 2^k for form 2,
+ *                      2 * 64 * r for form 3 (8192 always suffice),
  * where the A_a are the caller's operators with their local bits reordered to
  * ascending target order and, in the Heisenberg picture, adjoined.  The
  * native form is reported whenever the op has it (as for an operator beyond

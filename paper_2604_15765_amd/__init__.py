@@ -174,10 +174,13 @@ def prepare_op(n: int, tile_log2: int, targets: Sequence[int], mats, picture: in
     st = np.zeros(3, dtype=np.int32)
     nc = ctypes.c_int()
     form = ctypes.c_int()
-    coef = np.zeros(2 * 256, dtype=np.float64)
+    coef = np.zeros(2 * 64 * 64, dtype=np.float64)
     _check(lib.ht_prepare_op(n, tile_log2, k, _ptr(t), mats.shape[0], _ptr(mats), picture,
                              _ptr(st), ctypes.byref(nc), ctypes.byref(form), _ptr(coef)))
     d = 1 << k
+    if form.value == 3:  # k = 3 Kraus form: the operators themselves
+        c = coef[:2 * mats.shape[0] * d * d].view(np.complex128)
+        return (list(st[:k]), nc.value, form.value, c.reshape(mats.shape[0], d, d).copy())
     ne = d ** 4 if form.value == 1 else d * d
     c = coef[:2 * ne].view(np.complex128)
     side = d * d if form.value == 1 else d

@@ -29,7 +29,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast"]
 
-LIB_SOURCES = ["ht_conj.hip", "ht_native.hip", "ht_misc.hip", "ht_batch.hip", "ht_api.cpp",
+LIB_SOURCES = ["ht_conj.hip", "ht_native.hip", "ht_k3.hip", "ht_misc.hip", "ht_batch.hip", "ht_api.cpp",
                "ht_batch_api.cpp", "ht_circuit.cpp", "ht_batch_runner.cpp", "ht_autotune.cpp",
                "ht_fuse.cpp", "ht_server.cpp", "ht_prep.cpp"]
 LIB = os.path.join(HERE, "libhermtile.so")

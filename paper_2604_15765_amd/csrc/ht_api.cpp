@@ -124,6 +124,8 @@ constexpr int kMaxPauliTerms = 4096;
 ht_status ht_launch_prepared(ht_herm* h, const ht::PreparedOp& op) {
   ht_device_guard dg(h->device);
   if (op.k == 2 && op.form == 1) HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 512, h->stream));
+  if (op.form == ht::kFormKraus3)
+    HT_HIP(ht::launch_upload(h->coef_dev, op.coef, 128 * op.nkraus, h->stream));
   if (op.form == 2) {
     double data[512];
     const int nd = ht::native_op_data(op, data);
@@ -144,8 +146,9 @@ ht_status ht_launch_prepared(ht_herm* h, const ht::PreparedOp& op) {
     if (e != hipSuccess) return fail(e, "hipEventRecord");
   }
   const hipError_t e =
-      op.form == 2
-          ? ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream)
+      op.form == 2 ? ht::launch_native(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream)
+      : op.form == ht::kFormKraus3
+          ? ht::launch_k3(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream)
           : ht::launch_conj(h->dtype, h->buf, h->n, h->m, op, h->coef_dev, h->num_cu, h->stream);
   if (e != hipSuccess) return fail(e, "conjugation pass launch");
   if (h->prof) {
@@ -220,7 +223,7 @@ ht_status ht_herm_create(int n, int tile_log2, ht_dtype dtype, void* dev_buf, si
     }
     h->owned = true;
   }
-  if (hipMalloc(&h->coef_dev, 512 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&h->coef_dev, ht::kPrepCoefDoubles * sizeof(double)) != hipSuccess) {
     h->coef_dev = nullptr;
     return cleanup(ht_fail(HT_ENOMEM, "could not allocate coefficient buffer"));
   }
@@ -436,12 +439,6 @@ ht_status ht_herm_copy(ht_herm* dst, const ht_herm* src) {
   return HT_OK;
 }
 
-// A k = 3 operation outside the native form is valid input the library does
-// not implement; every other preparation failure is an invalid argument.
-static ht_status op_error(int prep_result) {
-  return prep_result == ht::kPrepUnsupported ? HT_EUNSUPPORTED : HT_EINVAL;
-}
-
 static ht_status apply(ht_herm* h, int k, const int* targets, int r, const double* mats,
                        ht_picture picture) {
   if (!h) return ht_fail(HT_EINVAL, "handle is NULL");
@@ -451,7 +448,7 @@ static ht_status apply(ht_herm* h, int k, const int* targets, int r, const doubl
   char msg[256];
   const int pr = ht::prepare_op(h->n, h->m, k, targets, r, mats, picture == HT_HEISENBERG, &op, msg,
                                 sizeof msg, ht::native_policy(h->bytes));
-  if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
+  if (pr != 0) return ht_fail(HT_EINVAL, "%s", msg);
   return ht_launch_prepared(h, op);
 }
 
@@ -574,7 +571,8 @@ const char* ht_kernel_class_name(int idx) {
       "k1_c0_direct", "k1_c0_transfer", "k1_c1_direct", "k1_c1_transfer", "k2_c0_direct",
       "k2_c0_transfer", "k2_c1_direct", "k2_c1_transfer", "k2_c2_direct", "k2_c2_transfer",
       "k1_c0_native", "k1_c1_native", "k2_c0_native", "k2_c1_native", "k2_c2_native",
-      "k3_c0_native", "k3_c1_native", "k3_c2_native", "k3_c3_native"};
+      "k3_c0_native", "k3_c1_native", "k3_c2_native", "k3_c3_native",
+      "k3_c0_kraus", "k3_c1_kraus", "k3_c2_kraus", "k3_c3_kraus"};
   static std::string full[2 * ht::kClassesPerDtype];
   static std::once_flag once;
   std::call_once(once, [] {
@@ -634,14 +632,14 @@ ht_status ht_prepare_op(int n, int tile_log2, int k, const int* targets, int r,
   char msg[256];
   const int pr = ht::prepare_op(n, m, k, targets, r, kraus, picture == HT_HEISENBERG, &op, msg,
                                 sizeof msg, ht::tuning().native != 0 ? 1 : 0);
-  if (pr != 0) return ht_fail(op_error(pr), "%s", msg);
+  if (pr != 0) return ht_fail(HT_EINVAL, "%s", msg);
   if (sorted_targets)
     for (int l = 0; l < op.k; ++l) sorted_targets[l] = op.sorted[l];
   if (ncross) *ncross = op.ncross;
   if (form) *form = op.form;
   if (coef) {
     const int D = 1 << op.k;
-    const int ne = op.form == 1 ? D * D * D * D : D * D;
+    const int ne = op.form == 1 ? D * D * D * D : op.form == ht::kFormKraus3 ? op.nkraus * D * D : D * D;
     std::memcpy(coef, op.coef, sizeof(double) * 2 * ne);
     if (op.form == 2)
       for (int u = 0; u < D; ++u) coef[2 * ne + u] = (double)op.perm[u];

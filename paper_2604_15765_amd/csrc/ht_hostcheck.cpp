@@ -11,6 +11,7 @@
 
 #include "ht_geom.h"
 #include "ht_internal.h"
+#include "ht_k3.h"
 #include "ht_native.h"
 #include "ht_prep.h"
 
@@ -71,6 +72,46 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
           ht::conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane, j0, j0 + JU);
       }
       ++*lanes_run;
+    }
+  }
+}
+
+// The k = 3 Kraus form (ht_k3.h): 8 lanes share a block and exchange their
+// left products through LDS, so the 64 lanes of a wave run here phase by
+// phase -- every lane's left products written to the 8 blocks' tables, then
+// every lane's row read back and its right products.
+template <int C>
+void run_k3(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, uint64_t* lanes_run) {
+  const ht::ConjGeom<3, C> g = ht::make_geom<3, C>(n, m, op.sorted, false);
+  const uint32_t nblk = 1u << (2 * g.F);
+  for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
+    const ht::K3Group gr = ht::k3_group<C>(grp);
+    ht::K3Tiles<C> tiles[8];
+    for (int j = 0; j < 8; ++j) ht::k3_tiles<C>(g, gr, j, tiles[j]);
+    for (uint32_t b0 = 0; b0 < nblk; b0 += 8) {
+      ht::K3Block bk[64];
+      ht::cd x[64][8], w[64][8], table[8][8][8];
+      for (uint32_t lane = 0; lane < 64; ++lane) {
+        bk[lane] = ht::k3_block<C>(g, gr, b0 + (lane >> 3));
+        for (int u = 0; u < 8; ++u) x[lane][u] = w[lane][u] = ht::cd{0.0, 0.0};
+        if (bk[lane].active) ht::k3_load_col<C>(mem, g, tiles[lane & 7], bk[lane], (int)(lane & 7), x[lane]);
+      }
+      for (int a = 0; a < op.nkraus; ++a) {
+        const double* Aa = op.coef + 128 * a;
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+          ht::cd t[8];
+          ht::k3_left(Aa, x[lane], t);
+          for (int u = 0; u < 8; ++u) table[lane >> 3][u][lane & 7] = t[u];
+        }
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+          ht::cd t[8];
+          for (int l = 0; l < 8; ++l) t[l] = table[lane >> 3][lane & 7][l];
+          ht::k3_right_acc(Aa, t, w[lane]);
+        }
+      }
+      for (uint32_t lane = 0; lane < 64; ++lane)
+        if (bk[lane].active) ht::k3_store_row<C>(mem, g, gr, tiles[lane & 7], bk[lane], (int)(lane & 7), w[lane]);
+      *lanes_run += 64;
     }
   }
 }
@@ -147,6 +188,12 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   HT_CASE(2, 2, 0)
   HT_CASE(2, 2, 1)
 #undef HT_CASE
+  if (op.form == ht::kFormKraus3) {
+    if (op.ncross == 0) run_k3<0>(mem, n, m, op, &lanes);
+    if (op.ncross == 1) run_k3<1>(mem, n, m, op, &lanes);
+    if (op.ncross == 2) run_k3<2>(mem, n, m, op, &lanes);
+    if (op.ncross == 3) run_k3<3>(mem, n, m, op, &lanes);
+  }
 #define HT_NATIVE(K_, C_) \
   if (op.form == 2 && op.k == K_ && op.ncross == C_) run_native<K_, C_>(mem, n, m, op, order, ilv != 0, &lanes);
   HT_NATIVE(1, 0)

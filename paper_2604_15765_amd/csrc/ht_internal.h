@@ -10,12 +10,13 @@
 namespace ht {
 
 // Number of kernel classes per dtype: (k, c, form) with c <= k.
-constexpr int kClassesPerDtype = 19;
+constexpr int kClassesPerDtype = 23;
 // Class index of (k, c, form) within a dtype: k=1 -> c*2+form (0..3),
 // k=2 -> 4 + c*2 + form (4..9); native form (2): k=1 -> 10 + c,
-// k=2 -> 12 + c, k=3 -> 15 + c (10..18).
+// k=2 -> 12 + c, k=3 -> 15 + c (10..18); k = 3 Kraus form: 19 + c (19..22).
 inline int conj_class(int k, int c, int form) {
   if (form == 2) return 10 + (k == 1 ? c : k == 2 ? 2 + c : 5 + c);
+  if (form == kFormKraus3) return 19 + c;
   return (k == 1 ? 0 : 4) + c * 2 + form;
 }
 
@@ -50,6 +51,11 @@ inline bool use_interleave(int /*entry_bytes*/) { return tuning().interleave != 
 // coefficients from memory (two-qubit transfer form); the caller uploads it.
 hipError_t launch_conj(int dtype, void* buf, int n, int m, const PreparedOp& op,
                        const double* coef_dev, int num_cu, hipStream_t s);
+
+// Enqueue one k = 3 Kraus-form pass (op.form == kFormKraus3); coef_dev holds
+// op.coef's 128 * op.nkraus doubles (uploaded by the caller).
+hipError_t launch_k3(int dtype, void* buf, int n, int m, const PreparedOp& op,
+                     const double* coef_dev, int num_cu, hipStream_t s);
 
 // Enqueue one native pass (op.form == 2); coef_dev holds what native_op_data
 // wrote (uploaded by the caller).
@@ -136,7 +142,7 @@ hipError_t launch_batch(int dtype, const BatchOperator* opers, unsigned nopers, 
 // Allow the batch kernel to use up to bytes of dynamic LDS.
 hipError_t set_batch_lds_limit(int dtype, size_t bytes);
 
-// Upload up to 512 doubles into a device buffer with stream-ordered kernels
+// Upload count doubles into a device buffer with stream-ordered kernels
 // (the values travel as kernel arguments, so no host buffer must outlive the
 // call and no pageable-memory copy is involved).
 hipError_t launch_upload(double* dst, const double* src, int count, hipStream_t s);

@@ -216,10 +216,15 @@ int prepare_op(int n, int m_eff, int k, const int* targets, int r, const double*
     if (st < 0) return 1;
     if (st == 1) return 0;
   }
-  if (k == 3) {
-    fail("k = 3 is supported for permutation-and-phase operations only (one nonzero "
-         "per row of every Kraus operator, in the same column for all of them)");
-    return kPrepUnsupported;
+  if (k == 3) {  // the Kraus operators themselves (a 64 x 64 transfer matrix would not pay)
+    out->form = kFormKraus3;
+    out->nkraus = r;
+    for (int a = 0; a < r; ++a)
+      for (int e = 0; e < D * D; ++e) {
+        out->coef[2 * (a * D * D + e)] = A[a][e].real();
+        out->coef[2 * (a * D * D + e) + 1] = A[a][e].imag();
+      }
+    return 0;
   }
 
   if (r == 1) {

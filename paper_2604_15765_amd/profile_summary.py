@@ -46,15 +46,20 @@ def _csv(d, suffix):
 
 def kernel_class(name: str):
     """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct',
-    'native_kernel<float, 3, 2, 0>' -> 'c64_k3_c2_native'; None otherwise."""
+    'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
+    'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus'; None otherwise."""
     m = re.search(r"conj_kernel<(double|float), (\d), (\d), (\d), (\d)>", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k{m.group(2)}_c{m.group(3)}_{'direct' if m.group(4) == '0' else 'transfer'}"
-    m = re.search(r"native_kernel<(double|float), (\d), (\d), (\d)>", name)
+    m = re.search(r"native_kernel<(double|float), (\d), (\d), (\d)", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k{m.group(2)}_c{m.group(3)}_native"
+    m = re.search(r"k3_kernel<(double|float), (\d), (\d)>", name)
+    if m:
+        dt = "c128" if m.group(1) == "double" else "c64"
+        return f"{dt}_k3_c{m.group(2)}_kraus"
     return None
 
 

@@ -105,10 +105,20 @@ def test_prepare_op_rejects_bad_arguments(ht):
         with pytest.raises(ht.HermError) as ei:
             ht.prepare_op(4, 2, t, bad.get("mats", U))
         assert ei.value.status == 1
-    # k = 3 exists only in the permutation-and-phase form
-    with pytest.raises(ht.HermError) as ei:
-        ht.prepare_op(4, 2, [0, 1, 2], synth.haar_unitary(8, synth.make_rng(3)))
-    assert ei.value.status == 4
+    # a general k = 3 op takes the Kraus form: the operators, renumbered to
+    # ascending targets (local bit l <- targets[l]) and adjoined in the
+    # Heisenberg picture
+    rng = synth.make_rng(3)
+    U = synth.haar_unitary(8, rng)
+    st, nc, form, coef = ht.prepare_op(5, 2, [4, 0, 2], U)
+    assert (st, nc, form, coef.shape) == ([0, 2, 4], 2, 3, (1, 8, 8))
+    perm = [sum(((v >> l) & 1) << [1, 2, 0][l] for l in range(3)) for v in range(8)]  # sorted bit -> user bit
+    assert np.allclose(coef[0], U[np.ix_(perm, perm)], rtol=0, atol=0)
+    K = synth.random_kraus_set(3, 5, rng)
+    _, _, form, coef = ht.prepare_op(5, 5, [0, 1, 2], K, picture=1)
+    assert form == 3 and np.array_equal(coef, np.conj(np.transpose(K, (0, 2, 1))))
+    with pytest.raises(ht.HermError):
+        ht.prepare_op(4, 2, [0, 1, 2], np.stack([np.eye(8)] * 65))  # r > 4^k
     with pytest.raises(ht.HermError):
         ht.prepare_op(4, 2, [0], np.stack([np.eye(2)] * 5))  # r > 4^k
     with pytest.raises(ht.HermError):
@@ -155,8 +165,8 @@ def test_native_tuning_switch(ht):
     try:
         ht.set_tuning("native", 0)
         assert ht.prepare_op(4, 2, [1], synth.named_gate("Z"))[2] == 0
-        with pytest.raises(ht.HermError):  # k = 3 has no generic form
-            ht.prepare_op(4, 2, [0, 1, 2], synth.permutation_gate("TOFFOLI"))
+        # without the native pass k = 3 permutations take the Kraus form
+        assert ht.prepare_op(4, 2, [0, 1, 2], synth.permutation_gate("TOFFOLI"))[2] == 3
     finally:
         ht.set_tuning("native", 1)
     assert ht.prepare_op(4, 2, [1], synth.named_gate("Z"))[2] == 2
@@ -181,8 +191,9 @@ def test_tuning_validation(ht):
 
 def test_kernel_class_names(ht):
     names = ht.kernel_class_names()
-    assert len(names) == 38 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k3_c3_native"
-    assert names[10] == "c128_k1_c0_native" and names[19] == "c64_k1_c0_direct"
+    assert len(names) == 46 and names[0] == "c128_k1_c0_direct" and names[-1] == "c64_k3_c3_kraus"
+    assert names[10] == "c128_k1_c0_native" and names[19] == "c128_k3_c0_kraus"
+    assert names[23] == "c64_k1_c0_direct"
 
 
 def _c_layout(struct, fields, tmp_path):

@@ -139,13 +139,58 @@ def test_toffoli_circuit_and_involutions(ht):
         assert np.array_equal(h.raw_entries(), raw)
 
 
-def test_k3_generic_matrix_is_unsupported_and_state_untouched(ht):
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_k3_kraus_form_matches_oracle(ht, m):
+    """General three-qubit unitaries and channels (the Kraus-form pass: 8
+    lanes per block, LDS exchange) against the oracle at n = 3..8 on sampled
+    target triples, both pictures, complex128 and complex64."""
+    rng = synth.make_rng(1750 + m)
+    for n in range(3, 9):
+        tuples = list(itertools.permutations(range(n), 3))
+        tuples = [tuples[i] for i in rng.choice(len(tuples), min(len(tuples), 10), replace=False)]
+        for t in tuples:
+            for kraus in (synth.haar_unitary(8, rng)[None], synth.random_kraus_set(3, int(rng.integers(2, 7)), rng)):
+                pic = int(rng.integers(2))
+                H, h, _ = _run(ht, n, m, list(t), kraus, pic, rng)
+                ref = (oracle.kraus_map_adjoint if pic else oracle.kraus_map)(H, kraus, list(t))
+                assert rel(h.to_dense(), ref) <= TOL, (n, m, t, kraus.shape[0], pic)
+        t = [int(x) for x in rng.choice(n, 3, replace=False)]
+        kraus = synth.random_kraus_set(3, 3, rng)
+        H, h, _ = _run(ht, n, m, t, kraus, 0, rng, dtype="c64")
+        e = rel(h.to_dense(), oracle.kraus_map(H.astype(np.complex64).astype(np.complex128), kraus, t))
+        assert e <= 2 * 2.0 ** -24, (n, m, t, e)
+
+
+def test_k3_kraus_form_agrees_with_native_pass(ht):
+    """A Toffoli and a random permutation-and-phase matrix through the Kraus
+    form (native pass off) and the native pass; a channel of full rank 64."""
+    rng = synth.make_rng(1760)
+    n, m = 8, 3
+    H = synth.random_hermitian_dense(n, rng)
+    try:
+        for t, U in (([0, 5, 7], synth.permutation_gate("TOFFOLI")), ([6, 2, 3], synth.random_monomial(3, rng))):
+            outs = []
+            for native in (0, 2):
+                ht.set_tuning("native", native)
+                h = ht.Herm(n, m).init_dense(H)
+                h.apply_unitary(t, U)
+                outs.append(h.to_dense())
+            assert rel(outs[0], outs[1]) <= 1e-14, t
+    finally:
+        ht.set_tuning("native", 2)
+    K = synth.random_kraus_set(3, 64, rng)
+    h = ht.Herm(n, m).init_dense(H)
+    h.apply_channel([7, 0, 4], K)
+    assert rel(h.to_dense(), oracle.kraus_map(H, K, [7, 0, 4])) <= TOL
+
+
+def test_k3_bad_kraus_count_leaves_state(ht):
     rng = synth.make_rng(1700)
     h = ht.Herm(6, 3).init_dense(synth.random_hermitian_dense(6, rng))
     raw = h.raw_entries()
     with pytest.raises(ht.HermError) as ei:
-        h.apply_unitary([0, 2, 5], synth.haar_unitary(8, rng))
-    assert ei.value.status == 4
+        h.apply_channel([0, 2, 5], np.stack([np.eye(8)] * 65))
+    assert ei.value.status == 1
     assert np.array_equal(h.raw_entries(), raw)
 
 
@@ -166,6 +211,8 @@ def test_native_full_size_sampled_blocks(ht, n):
         synth.random_ops.unitary_op([0, 8, n - 1], synth.permutation_gate("FREDKIN")),
         synth.random_ops.unitary_op([n - 1, 10, 5], synth.permutation_gate("TOFFOLI")),
         synth.random_ops.unitary_op([6, 11, 12], synth.random_monomial(3, rng)),
+        synth.random_ops.unitary_op([2, n - 2, 9], synth.haar_unitary(8, rng)),       # Kraus form
+        synth.random_ops.channel_op([n - 1, 0, 6], synth.random_kraus_set(3, 2, rng)),  # Kraus form
     ]
     for i, op in enumerate(ops):
         k = len(op.targets)

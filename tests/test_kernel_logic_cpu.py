@@ -273,14 +273,40 @@ def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
         assert form in (0, 1), (t, form)
 
 
-def test_three_qubit_ops_need_the_native_form(hc):
-    rng = synth.make_rng(960)
-    n, m = 4, 2
-    raw = np.ascontiguousarray(layout.encode(synth.random_hermitian_dense(n, rng), m))
-    kraus = np.ascontiguousarray(synth.haar_unitary(8, rng)[None])
-    t = np.array([0, 1, 3], dtype=np.int32)
-    err = ctypes.create_string_buffer(256)
-    lanes = ctypes.c_uint64()
-    rc = hc(raw.ctypes.data, raw.size, n, m, 3, t.ctypes.data, 1, kraus.ctypes.data, 0, None, None,
-            ctypes.byref(lanes), 0, 1, 0, None, err, 256)
-    assert rc == 1 and b"k = 3" in err.value
+# ----------------------------------------------- k = 3 Kraus form (form 3)
+
+def check_k3(f, n, m, targets, kraus, heis, rng, native=0):
+    H = synth.random_hermitian_dense(n, rng)
+    raw = layout.encode(H, m)
+    out, wc, form = emulate(f, raw, n, m, targets, kraus, heis, native=native, want_form=True)
+    assert form == 3, (targets, form)
+    assert np.all(wc == 1), (n, m, targets, np.unique(wc))
+    e = rel(layout.decode(out, n, m), reference(H, kraus, targets, heis))
+    assert e < 1e-13, (n, m, targets, kraus.shape[0], heis, e)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_k3_kraus_form_every_triple(hc, m):
+    """General three-qubit unitaries and channels (8 lanes per block, the
+    LDS exchange emulated phase by phase) on every ordered triple at
+    n = 3..5 and a sample at n = 6, 7: every stored entry written once,
+    results vs the oracle, both pictures, every count of tile-selecting
+    targets."""
+    rng = synth.make_rng(1100 + m)
+    for n in range(3, 8):
+        triples = list(itertools.permutations(range(n), 3))
+        if n >= 6:
+            triples = [triples[i] for i in rng.choice(len(triples), 12, replace=False)]
+        for t in triples:
+            heis = bool(rng.integers(2))
+            check_k3(hc, n, m, list(t), synth.haar_unitary(8, rng)[None], heis, rng)
+            check_k3(hc, n, m, list(t), synth.random_kraus_set(3, int(rng.integers(2, 6)), rng), heis, rng)
+
+
+def test_k3_kraus_form_full_rank_and_permutations(hc):
+    """A channel with 64 Kraus operators (the largest rank), and a Toffoli
+    with the native pass off: the Kraus form gives the oracle's result."""
+    rng = synth.make_rng(1200)
+    n, m = 7, 5
+    check_k3(hc, n, m, [6, 1, 5], synth.random_kraus_set(3, 64, rng), False, rng)
+    check_k3(hc, n, m, [2, 6, 0], synth.permutation_gate("TOFFOLI")[None], True, rng, native=0)
