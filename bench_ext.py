@@ -314,7 +314,9 @@ def run_serve(args):
 def run_native(args):
     """Permutation-and-phase gates at n = 16, c128, tile edge 32: each gate
     at intra and tile-selecting positions, timed with the native pass and
-    with the generic pass (native off), on the same operator."""
+    with the generic pass (native off; for k = 3 the Kraus form), on the
+    same operator; and general three-qubit unitaries and channels (Kraus
+    form)."""
     import torch
     import paper_2604_15765_amd as ht
     import synth
@@ -336,13 +338,20 @@ def run_native(args):
         ("CCZ", [7, 9, 15], synth.permutation_gate("CCZ")),
         ("FREDKIN", [5, 11, 13], synth.permutation_gate("FREDKIN")),
     ]
+    # general three-qubit ops (no native form): the Kraus-form pass
+    kraus3 = [
+        ("haar8", [2, 3, 4], synth.haar_unitary(8, rng)), ("haar8", [0, 1, 2], synth.haar_unitary(8, rng)),
+        ("haar8", [3, 4, 12], synth.haar_unitary(8, rng)), ("haar8", [5, 10, 15], synth.haar_unitary(8, rng)),
+        ("kraus3_r2", [3, 8, 12], synth.random_kraus_set(3, 2, rng)),
+        ("kraus3_r4", [3, 8, 12], synth.random_kraus_set(3, 4, rng)),
+        ("kraus3_r8", [3, 8, 12], synth.random_kraus_set(3, 8, rng)),
+    ]
     results = []
-    for name, t, g in cases:
+    for name, t, g in cases + kraus3:
         kraus = g if g.ndim == 3 else g[None]
         row = {"gate": name, "targets": t}
-        for native in (1, 0):
-            if native == 0 and len(t) == 3:
-                continue  # k = 3 exists only in the native form
+        for native in ((1,) if name.startswith(("haar8", "kraus3")) else (1, 0)):
+            # native 0: the generic pass (k <= 2) or the Kraus form (k = 3)
             ht.set_tuning("native", native)
             for _ in range(2):
                 h.apply_channel(t, kraus)
@@ -353,12 +362,12 @@ def run_native(args):
             prof = h.profile_read()
             h.profile_enable(False)
             (cls, v), = prof.items()
-            key = "native" if native else "generic"
+            key = "native" if native and cls.endswith("native") else "generic"
             row[key] = {"class": cls, "avg_ms": v["ms"] / v["launches"],
                         "bytes_per_launch": v["bytes"] / v["launches"],
                         "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
         ht.set_tuning("native", 1)
-        if "generic" in row:
+        if "generic" in row and "native" in row:
             row["speedup"] = row["generic"]["avg_ms"] / row["native"]["avg_ms"]
         log(f"[native] {row}")
         results.append(row)

@@ -196,10 +196,12 @@ ht_status ht_apply_unitary(ht_herm* h, int k, const int* targets, const double* 
  * Schroedinger H -> sum_a L_a H L_a^dagger (Eq. (1)), Heisenberg
  * H -> sum_a L_a^dagger H L_a.  k in {1, 2, 3}; 1 <= r <= 4^k; kraus: host,
  * r consecutive 2^k x 2^k row-major complex matrices (2 * r * 4^k doubles).
- * For r > 1 the map is applied through its transfer matrix (Eq. (3),
- * built on the host in FP64).  Kraus sets whose operators all have one
- * nonzero per row in the same columns (dephasing, for example) take the
- * native pass described at ht_apply_unitary; k = 3 only in that case.
+ * For r > 1 and k <= 2 the map is applied through its transfer matrix
+ * (Eq. (3), built on the host in FP64); for k = 3 as the sum of the r
+ * two-sided products (the Kraus-form pass described at ht_apply_unitary).
+ * Kraus sets whose operators all have one nonzero per row in the same
+ * columns (dephasing, for example) take the native pass described at
+ * ht_apply_unitary.
  * Trace-preservation is not required (the algorithms hold for trace
  * non-increasing maps, Section IV-A).  Enqueued asynchronously; kraus is
  * copied before return. */
