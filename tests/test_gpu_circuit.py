@@ -144,3 +144,29 @@ def test_apply_checks_qubits_and_leaves_state(ht):
     with pytest.raises(ht.HermError):
         ht.Circuit().apply(h)  # not planned
     c.close()
+
+
+def test_empty_inputs_are_no_ops(ht):
+    """An empty circuit, an empty batch and a circuit of one op on the
+    smallest operator (n = 1) leave or update the state as they should."""
+    rng = synth.make_rng(3100)
+    h = ht.Herm(5, 2).init_dense(synth.random_hermitian_dense(5, rng))
+    raw = h.raw_entries()
+    c = ht.Circuit()
+    assert c.plan(0, 2) == 0
+    c.apply(h)
+    b = ht.Batch()
+    b.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(h.raw_entries(), raw)
+    c.close()
+    b.close()
+    H1 = synth.random_hermitian_dense(1, rng)
+    ops = [synth.random_ops.unitary_op([0], synth.haar_unitary(2, rng)),
+           synth.random_ops.channel_op([0], synth.dephasing_kraus(0.3))]
+    c = ht.Circuit(ops)
+    assert c.plan(0, 2) == 1
+    h1 = ht.Herm(1, 5).init_dense(H1)
+    c.apply(h1)
+    assert rel(h1.to_dense(), oracle.apply_ops(H1, ops)) <= TOL
+    c.close()
