@@ -148,3 +148,26 @@ def test_server_fails_only_the_request_the_device_cannot_hold(ht):
     assert [res[i]["status"] for i in ids + [ok]] == [0] * (len(ids) + 1)
     assert [res[i]["value"] for i in ids] == want
     assert res[ok]["value"] == want[0]
+
+
+def test_server_heisenberg_requests(ht):
+    """Requests in the Heisenberg picture: every op applied as its adjoint
+    map, in the order given, in the batched, medium and large lanes and with
+    fusion; the readout matches the oracle."""
+    rng = synth.make_rng(85)
+    reqs = []
+    for n in (4, 6, 8, 9):
+        G = synth.ginibre_factor(n, 4, rng)
+        ops = [synth.circuits._random_mixed_op(n, rng, "dephase") for _ in range(25)]
+        reqs.append(dict(n=n, G=G, ops=ops, pauli=synth.random_pauli_sum(n, 8, rng)))
+    for cfg in (dict(batch_max_qubits=5, medium_max_qubits=8), dict(fuse_qubits=2)):
+        srv = ht.Server(**cfg)
+        ids = [srv.submit(r["n"], r["G"], r["ops"], r["pauli"], "c128", ht.HEISENBERG) for r in reqs]
+        srv.wait_idle(300)
+        res = {d["id"]: d for d in srv.poll()}
+        srv.close()
+        for i, r in zip(ids, reqs):
+            assert res[i]["status"] == 0
+            rho = oracle.apply_ops(oracle.density_from_factor(r["G"]), r["ops"], adjoint=True)
+            want = oracle.pauli_sum_expectation(rho, *r["pauli"])
+            assert abs(res[i]["value"] - want) <= 1e-12 * max(1.0, abs(want)), (cfg, r["n"])
