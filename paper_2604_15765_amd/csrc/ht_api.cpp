@@ -608,6 +608,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().interleave = (int)value;
     return HT_OK;
   }
+  if (k == "pairs") {
+    if (value < 0 || value > 2) return ht_fail(HT_EINVAL, "pairs must be 0, 1 or 2");
+    ht::tuning().pairs = (int)value;
+    return HT_OK;
+  }
   if (k == "native") {
     if (value < 0 || value > 2) return ht_fail(HT_EINVAL, "native must be 0, 1 or 2");
     ht::tuning().native = (int)value;

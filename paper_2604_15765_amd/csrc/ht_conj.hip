@@ -13,6 +13,7 @@
 // group are disjoint, so no synchronisation is needed.
 #include "ht_geom.h"
 #include "ht_internal.h"
+#include "ht_pair.h"
 
 namespace ht {
 
@@ -56,6 +57,87 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------------------------------- pair layout
+
+// Complex64 entries for the pair layout (ht_pair.h): single entries and
+// 16-byte pairs, held as FP64 values.  MODE as for DirectMem.
+template <int MODE>
+struct PairMem {
+  float2* __restrict__ h;
+  typedef float V2 __attribute__((ext_vector_type(2)));
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  template <typename V>
+  __device__ V* at(uint64_t tb, uint32_t off) const {
+    return reinterpret_cast<V*>(reinterpret_cast<char*>(h + tb) + (uint32_t)(off * 8u));
+  }
+  __device__ cd load(uint64_t tb, uint32_t off) const {
+    const V2 v = (MODE & 1) ? __builtin_nontemporal_load(at<V2>(tb, off)) : *at<V2>(tb, off);
+    return {(double)v.x, (double)v.y};
+  }
+  __device__ void load_pair(uint64_t tb, uint32_t off, cd& a, cd& b) const {
+    const V4 v = (MODE & 1) ? __builtin_nontemporal_load(at<V4>(tb, off)) : *at<V4>(tb, off);
+    a = {(double)v.x, (double)v.y};
+    b = {(double)v.z, (double)v.w};
+  }
+  __device__ void store(uint64_t tb, uint32_t off, cd w) const {
+    V2 v;
+    v.x = (float)w.re;
+    v.y = (float)w.im;
+    if constexpr ((MODE & 2) != 0)
+      __builtin_nontemporal_store(v, at<V2>(tb, off));
+    else
+      *at<V2>(tb, off) = v;
+  }
+  __device__ void store_pair(uint64_t tb, uint32_t off, cd a, cd b) const {
+    V4 v;
+    v.x = (float)a.re;
+    v.y = (float)a.im;
+    v.z = (float)b.re;
+    v.w = (float)b.im;
+    if constexpr ((MODE & 2) != 0)
+      __builtin_nontemporal_store(v, at<V4>(tb, off));
+    else
+      *at<V4>(tb, off) = v;
+  }
+};
+
+// The one-qubit pass on complex64 storage in the pair layout; groups on the
+// diagonal of the reduced grid take the block layout (same step count).
+template <int C, int FORM, int MODE>
+__global__ void __launch_bounds__(256)
+    pair_kernel(float2* __restrict__ h, ConjGeom<1, C> g, Coef<1, FORM> cf, int order) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const DirectMem<float, MODE, true> mem{h};
+  const PairMem<MODE> pm{h};
+  constexpr int JU = 4, JP = 2;  // blocks / pairs per lane and step: 16 entries either way
+  if (order == 0) {
+    for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
+      GroupCtx<C> gc;
+      group_ctx<1, C>(grp, g, gc);
+      if (gc.diag)
+        conj_group_lane<JU, 1, C, FORM>(mem, g, gc, cf, lane);
+      else
+        pair_group_lane<JP, C, FORM>(pm, g, gc, cf, lane, 0, 0xffffffffu);
+    }
+  } else {
+    const uint32_t steps = g.jobs / JU;  // = pair_jobs / JP, a power of two
+    const int sl = 31 - __builtin_clz(steps);
+    const uint64_t items = g.ngroups << sl;
+    for (uint64_t it = wave; it < items; it += nwaves) {
+      GroupCtx<C> gc;
+      group_ctx<1, C>(it >> sl, g, gc);
+      const uint32_t st = (uint32_t)(it & (steps - 1));
+      if (gc.diag)
+        conj_group_lane<JU, 1, C, FORM>(mem, g, gc, cf, lane, st * JU, st * JU + JU);
+      else
+        pair_group_lane<JP, C, FORM>(pm, g, gc, cf, lane, st * JP, st * JP + JP);
+    }
+  }
+}
+
 template <typename T, int K, int C, int FORM>
 static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const double* coef_dev,
                            int num_cu, hipStream_t s) {
@@ -79,6 +161,27 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
+  if constexpr (sizeof(T) == 4 && K == 1) {
+    // The pair layout needs a free column bit 0 and F >= 4.  Automatic use
+    // (pairs == 1) is limited to the targets where it measured faster at
+    // n = 16: intra targets at bit 4 or above, and cross targets below the
+    // top tile bit (intra targets 1..3 split the 16-byte accesses of a lane
+    // row across lines; at the top tile bit the block layout stays ahead).
+    const bool applies = g.F >= 4 && (C == 1 || g.ipos[0] != 0);
+    const bool pays = C == 1 ? g.cpos[0] < n - g.m - 1 : g.ipos[0] >= 4;
+    if (applies && (tuning().pairs == 2 || (tuning().pairs == 1 && pays))) {
+      // 16-byte accesses in direct tiles cover whole lines: nontemporal
+      const int pmode = tuning().mem_mode < 0 ? 3 : tuning().mem_mode;
+      const dim3 grid((unsigned)wgs), block(threads);
+      switch (pmode) {
+        case 1: hipLaunchKernelGGL((pair_kernel<C, FORM, 1>), grid, block, 0, s, hp, g, cf, order); break;
+        case 2: hipLaunchKernelGGL((pair_kernel<C, FORM, 2>), grid, block, 0, s, hp, g, cf, order); break;
+        case 3: hipLaunchKernelGGL((pair_kernel<C, FORM, 3>), grid, block, 0, s, hp, g, cf, order); break;
+        default: hipLaunchKernelGGL((pair_kernel<C, FORM, 0>), grid, block, 0, s, hp, g, cf, order);
+      }
+      return hipGetLastError();
+    }
+  }
   int mode = tuning().mem_mode;
   if (mode < 0) {
     // Nontemporal hints pay off only when every store instruction writes

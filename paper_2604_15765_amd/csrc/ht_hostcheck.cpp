@@ -13,6 +13,7 @@
 #include "ht_internal.h"
 #include "ht_k3.h"
 #include "ht_native.h"
+#include "ht_pair.h"
 #include "ht_prep.h"
 
 namespace {
@@ -49,11 +50,23 @@ struct CheckedMem {
     if (wc) wc[e]++;
     ht::store_c<double>(h + tb, off, v);
   }
+  // the pair layout's 16-byte accesses (ht_pair.h): entries off and off + 1;
+  // the GPU's accesses are 16-byte aligned, so off must be even
+  void load_pair(uint64_t tb, uint32_t off, ht::cd& a, ht::cd& b) const {
+    if (off & 1u) *oob = true;
+    a = load(tb, off);
+    b = load(tb, off + 1u);
+  }
+  void store_pair(uint64_t tb, uint32_t off, ht::cd a, ht::cd b) const {
+    if (off & 1u) *oob = true;
+    store(tb, off, a);
+    store(tb, off + 1u, b);
+  }
 };
 
 template <int JU, int K, int C, int FORM>
 void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int order, bool ilv,
-         uint64_t* lanes_run) {
+         bool pairs, uint64_t* lanes_run) {
   ht::ConjGeom<K, C> g = ht::make_geom<K, C>(n, m, op.sorted, ilv);
   ht::Coef<K, FORM> cf;
   if constexpr (K == 2 && FORM == 1) {
@@ -61,9 +74,27 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
   } else {
     for (int i = 0; i < 2 * ht::Coef<K, FORM>::NE; ++i) cf.c[i] = op.coef[i];
   }
+  // the pair layout of complex64 one-qubit passes, indexing checked on this
+  // complex128 copy (the same entries, in pairs)
+  bool use_pairs = false;
+  if constexpr (K == 1) use_pairs = pairs && g.F >= 4 && (C == 1 || g.ipos[0] != 0);
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
     ht::GroupCtx<C> gc;
     ht::group_ctx<K, C>(grp, g, gc);
+    if constexpr (K == 1) {
+      if (use_pairs && !gc.diag) {
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+          if (order == 0) {
+            ht::pair_group_lane<2, C, FORM>(mem, g, gc, cf, lane, 0, 0xffffffffu);
+          } else {
+            for (uint32_t j0 = 0; j0 < ht::pair_jobs(g.F); j0 += 2)
+              ht::pair_group_lane<2, C, FORM>(mem, g, gc, cf, lane, j0, j0 + 2);
+          }
+          ++*lanes_run;
+        }
+        continue;
+      }
+    }
     for (uint32_t lane = 0; lane < 64; ++lane) {
       if (order == 0) {
         ht::conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane);
@@ -158,14 +189,15 @@ extern "C" {
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
 // ranges of the flattened work order.  ilv: the alternating
-// patch order (lane_block).  native: allow the
+// patch order (lane_block).  pairs: the pair layout of complex64
+// one-qubit passes (ht_pair.h), checked on this complex128 copy.  native: allow the
 // native pass for permutation-and-phase operations; *form (if not NULL)
 // receives the form used.  Returns 0 on success, 1 on invalid op, 2 on an
 // out-of-range access.  *lanes_run receives the number of lane bodies run.
 int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, const int* targets,
                      int r, const double* kraus, int heisenberg, int32_t* write_counts,
                      int32_t* read_counts, uint64_t* lanes_run, int order, int native,
-                     int ilv, int* form, char* err, size_t errlen) {
+                     int ilv, int pairs, int* form, char* err, size_t errlen) {
   const int m = tile_log2 < n ? tile_log2 : n;
   ht::PreparedOp op;
   if (ht::prepare_op(n, m, k, targets, r, kraus, heisenberg, &op, err, errlen, native) != 0)
@@ -176,7 +208,7 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   uint64_t lanes = 0;
 #define HT_CASE(K_, C_, F_)                                 \
   if (op.k == K_ && op.ncross == C_ && op.form == F_)       \
-    run<ht::conj_unroll(K_), K_, C_, F_>(mem, n, m, op, order, ilv != 0, &lanes);
+    run<ht::conj_unroll(K_), K_, C_, F_>(mem, n, m, op, order, ilv != 0, pairs != 0, &lanes);
   HT_CASE(1, 0, 0)
   HT_CASE(1, 0, 1)
   HT_CASE(1, 1, 0)

@@ -431,6 +431,37 @@ def test_c64_single_ops_within_one_rounding(ht, m):
             assert e <= 2 * C64_EPS, (targets, kraus.shape[0], e)
 
 
+def test_c64_pair_layout_is_bitwise_equal_to_the_block_layout(ht):
+    """The pair layout of complex64 one-qubit passes (two blocks in adjacent
+    columns per lane, 16-byte accesses) applies the same FP64 arithmetic to
+    every block as the block layout: bitwise equal storage for every target
+    it applies to, both work orders, unitaries and channels, and within one
+    rounding of the oracle."""
+    rng = synth.make_rng(720)
+    n = 9
+    H = synth.random_hermitian_dense(n, rng)
+    Hq = lower_hermitian(quantise_c64(H))
+    try:
+        for m in (5, 6):
+            for a in range(1, n):
+                for kraus in (synth.haar_unitary(2, rng)[None], synth.random_kraus_set(1, 3, rng)):
+                    out = []
+                    for pairs, order in ((0, 0), (2, 0), (2, 1)):
+                        ht.set_tuning("pairs", pairs)
+                        ht.set_tuning("conj_order", order)
+                        h = make(ht, n, m, H, dtype="c64")
+                        h.apply_channel([a], kraus)
+                        out.append((h.raw_entries(), h.to_dense()))
+                        h.close()
+                    assert np.array_equal(out[0][0], out[1][0]), (m, a)
+                    assert np.array_equal(out[0][0], out[2][0]), (m, a)
+                    e = rel(out[1][1], oracle.kraus_map(Hq, kraus, [a]))
+                    assert e <= 2 * C64_EPS, (m, a, e)
+    finally:
+        ht.set_tuning("pairs", 1)
+        ht.set_tuning("conj_order", -1)
+
+
 def test_c64_circuit_error_bound_and_fp64_reductions(ht):
     """The n = 8 circuit in complex64 storage: error vs the FP64 oracle stays
     within (passes + 1) * 2^-24 relative (one rounding per pass plus the

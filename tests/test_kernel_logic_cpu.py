@@ -35,15 +35,16 @@ def hc():
     vp = ctypes.c_void_p
     f.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp,
                   ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_int,
-                  ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, ctypes.c_size_t]
+                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, ctypes.c_size_t]
     f.restype = ctypes.c_int
     return f
 
 
-def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=False, ilv=0):
+def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=False, ilv=0, pairs=0):
     """Run one pass on the CPU.  native=0 keeps the generic forms (direct,
     transfer); native=1 lets permutation-and-phase ops take the native pass;
-    ilv=1 the alternating patch order."""
+    ilv=1 the alternating patch order; pairs=1 the pair layout of complex64
+    one-qubit passes (indexing checked on complex128 storage)."""
     raw = np.ascontiguousarray(raw, dtype=np.complex128).copy()
     kraus = np.ascontiguousarray(kraus, dtype=np.complex128)
     t = np.ascontiguousarray(targets, dtype=np.int32)
@@ -52,8 +53,8 @@ def emulate(f, raw, n, m, targets, kraus, heis, order=0, native=0, want_form=Fal
     form = ctypes.c_int(-1)
     err = ctypes.create_string_buffer(256)
     rc = f(raw.ctypes.data, raw.size, n, m, len(targets), t.ctypes.data, kraus.shape[0], kraus.ctypes.data,
-           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, native, ilv, ctypes.byref(form), err,
-           256)
+           int(heis), wc.ctypes.data, None, ctypes.byref(lanes), order, native, ilv, pairs, ctypes.byref(form),
+           err, 256)
     assert rc == 0, err.value.decode()
     if want_form:
         return raw, wc, form.value
@@ -73,7 +74,8 @@ def check(f, n, m, targets, kraus, heis, rng):
     raw = layout.encode(H, m)
     order = int(rng.integers(2))  # both work orders of the kernel
     ilv = int(rng.integers(2))    # both patch orders
-    out, wc = emulate(f, raw, n, m, targets, kraus, heis, order, ilv=ilv)
+    pairs = int(rng.integers(2))  # both layouts of complex64 one-qubit passes
+    out, wc = emulate(f, raw, n, m, targets, kraus, heis, order, ilv=ilv, pairs=pairs)
     assert np.all(wc == 1), f"write counts {np.unique(wc)} for n={n} m={m} t={targets}"
     got = layout.decode(out, n, m)
     ref = reference(H, kraus, targets, heis)
@@ -271,6 +273,29 @@ def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
     for t, g in cases:
         _, _, form = emulate(hc, raw, n, m, t, g, False, native=1, want_form=True)
         assert form in (0, 1), (t, form)
+
+
+# ------------------------------------------- pair layout (complex64, k = 1)
+
+@pytest.mark.parametrize("m", [4, 5, 6])
+def test_pair_layout_covers_every_entry_once(hc, m):
+    """The pair layout of complex64 one-qubit passes (two blocks in adjacent
+    columns per lane, 16-byte accesses in stored tiles): every entry read and
+    written once, 16-byte accesses aligned, results those of the block
+    layout, for intra and tile-selecting targets, both forms, both pictures
+    and both work orders (diagonal groups keep the block layout)."""
+    rng = synth.make_rng(1300 + m)
+    for n in (m + 1, m + 2):
+        H = synth.random_hermitian_dense(n, rng)
+        raw = layout.encode(H, m)
+        for a in range(1, n):
+            for kraus in (synth.haar_unitary(2, rng)[None], synth.random_kraus_set(1, 3, rng)):
+                heis = bool(rng.integers(2))
+                order = int(rng.integers(2))
+                p, wp = emulate(hc, raw, n, m, [a], kraus, heis, order, pairs=1)
+                b, _ = emulate(hc, raw, n, m, [a], kraus, heis, order, pairs=0)
+                assert np.all(wp == 1), (n, m, a, np.unique(wp))
+                assert np.array_equal(p, b), (n, m, a)
 
 
 # ----------------------------------------------- k = 3 Kraus form (form 3)
