@@ -47,7 +47,9 @@ def _csv(d, suffix):
 def kernel_class(name: str):
     """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct',
     'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
-    'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus'; None otherwise."""
+    'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus',
+    'pair_kernel<1, 0, 3>' -> 'c64_k1_c1_direct' (complex64 only); None
+    otherwise."""
     m = re.search(r"conj_kernel<(double|float), (\d), (\d), (\d), (\d)>", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
@@ -60,6 +62,9 @@ def kernel_class(name: str):
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k3_c{m.group(2)}_kraus"
+    m = re.search(r"pair_kernel<(\d), (\d), (\d)>", name)
+    if m:
+        return f"c64_k1_c{m.group(1)}_{'direct' if m.group(2) == '0' else 'transfer'}"
     return None
 
 
@@ -139,7 +144,7 @@ def read_traffic(path: str):
     out = {}
     for line in text.splitlines():
         parts = line.split()
-        if len(parts) == 5 and re.match(r"c(128|64)_k\d_c\d_(direct|transfer|native)$", parts[0]):
+        if len(parts) == 5 and re.match(r"c(128|64)_k\d_c\d_(direct|transfer|native|kraus)$", parts[0]):
             out[parts[0]] = float(parts[4]) * 1e9
     return out
 
