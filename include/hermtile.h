@@ -478,11 +478,11 @@ const char* ht_kernel_class_name(int idx);
  * default 1): the order in which a lane walks its patches of a tile group,
  * 1 alternating column and row patches (whole cache lines of 8-byte entries
  * in mirrored tiles too).  "pairs" (0, 1 or 2, default 1): the pair layout of
- * complex64 one-qubit passes, in which a lane holds two blocks in adjacent
- * columns and moves their entries as 16-byte accesses; 0 off, 1 where it pays
- * (intra targets at bit 4 or above, cross targets below the top tile bit),
- * 2 wherever it applies (no intra target at bit 0, at least 4 free bits per
- * tile dimension).  HT_EINVAL for an unknown name or value.  Set it
+ * complex64 passes (one-qubit ops, and two-qubit ops in the direct form), in
+ * which a lane holds two blocks in adjacent columns and moves their entries
+ * as 16-byte accesses; 0 off, 1 where it pays (every target tile-selecting,
+ * or the intra target at bit 4 or above), 2 wherever it applies (no intra
+ * target at bit 0, at least 4 free bits per tile dimension).  HT_EINVAL for an unknown name or value.  Set it
  * while no other thread enqueues work (a server's scheduler thread reads it). */
 ht_status ht_set_tuning(const char* name, int64_t value);
 

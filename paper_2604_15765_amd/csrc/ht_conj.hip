@@ -60,67 +60,107 @@ __global__ void __launch_bounds__(256)
 // ------------------------------------------------------------- pair layout
 
 // Complex64 entries for the pair layout (ht_pair.h): single entries and
-// 16-byte pairs, held as FP64 values.  MODE as for DirectMem.
-template <int MODE>
+// 16-byte pairs.  NARROW: a lane holds a loaded pair as it is stored (four
+// floats), else as two FP64 values.  MODE as for DirectMem.
+template <int MODE, bool NARROW>
 struct PairMem {
   float2* __restrict__ h;
   typedef float V2 __attribute__((ext_vector_type(2)));
   typedef float V4 __attribute__((ext_vector_type(4)));
+  struct Wide {
+    cd a, b;
+  };
+  using H = typename std::conditional<NARROW, V4, Wide>::type;
   template <typename V>
   __device__ V* at(uint64_t tb, uint32_t off) const {
     return reinterpret_cast<V*>(reinterpret_cast<char*>(h + tb) + (uint32_t)(off * 8u));
   }
-  __device__ cd load(uint64_t tb, uint32_t off) const {
-    const V2 v = (MODE & 1) ? __builtin_nontemporal_load(at<V2>(tb, off)) : *at<V2>(tb, off);
-    return {(double)v.x, (double)v.y};
-  }
-  __device__ void load_pair(uint64_t tb, uint32_t off, cd& a, cd& b) const {
-    const V4 v = (MODE & 1) ? __builtin_nontemporal_load(at<V4>(tb, off)) : *at<V4>(tb, off);
-    a = {(double)v.x, (double)v.y};
-    b = {(double)v.z, (double)v.w};
-  }
-  __device__ void store(uint64_t tb, uint32_t off, cd w) const {
-    V2 v;
-    v.x = (float)w.re;
-    v.y = (float)w.im;
-    if constexpr ((MODE & 2) != 0)
-      __builtin_nontemporal_store(v, at<V2>(tb, off));
+  template <typename V>
+  __device__ V ld(uint64_t tb, uint32_t off) const {
+    if constexpr ((MODE & 1) != 0)
+      return __builtin_nontemporal_load(at<V>(tb, off));
     else
-      *at<V2>(tb, off) = v;
+      return *at<V>(tb, off);
   }
-  __device__ void store_pair(uint64_t tb, uint32_t off, cd a, cd b) const {
-    V4 v;
-    v.x = (float)a.re;
-    v.y = (float)a.im;
-    v.z = (float)b.re;
-    v.w = (float)b.im;
+  template <typename V>
+  __device__ void st(uint64_t tb, uint32_t off, V v) const {
     if constexpr ((MODE & 2) != 0)
-      __builtin_nontemporal_store(v, at<V4>(tb, off));
+      __builtin_nontemporal_store(v, at<V>(tb, off));
     else
-      *at<V4>(tb, off) = v;
+      *at<V>(tb, off) = v;
+  }
+  __device__ static H make(V4 v) {
+    if constexpr (NARROW)
+      return v;
+    else
+      return Wide{cd{(double)v.x, (double)v.y}, cd{(double)v.z, (double)v.w}};
+  }
+  __device__ static V4 narrow(const H& x) {
+    if constexpr (NARROW)
+      return x;
+    else
+      return V4{(float)x.a.re, (float)x.a.im, (float)x.b.re, (float)x.b.im};
+  }
+  __device__ H load_pair(uint64_t tb, uint32_t off) const { return make(ld<V4>(tb, off)); }
+  __device__ H load_two(uint64_t tb, uint32_t o0, uint32_t o1) const {
+    const V2 a = ld<V2>(tb, o0), b = ld<V2>(tb, o1);
+    return make(V4{a.x, a.y, b.x, b.y});
+  }
+  __device__ static void widen(const H& x, bool cj, cd& a, cd& b) {
+    if constexpr (NARROW) {
+      a = cd{(double)x.x, cj ? -(double)x.y : (double)x.y};
+      b = cd{(double)x.z, cj ? -(double)x.w : (double)x.w};
+    } else {
+      a = cj ? conjg(x.a) : x.a;
+      b = cj ? conjg(x.b) : x.b;
+    }
+  }
+  __device__ static void set(H& x, int i, cd w) {
+    if constexpr (NARROW) {
+      if (i == 0) {
+        x.x = (float)w.re;
+        x.y = (float)w.im;
+      } else {
+        x.z = (float)w.re;
+        x.w = (float)w.im;
+      }
+    } else {
+      (i == 0 ? x.a : x.b) = w;
+    }
+  }
+  __device__ void store_pair(uint64_t tb, uint32_t off, const H& x) const { st<V4>(tb, off, narrow(x)); }
+  __device__ void store_two_cj(uint64_t tb, uint32_t o0, uint32_t o1, const H& x) const {
+    const V4 v = narrow(x);
+    st<V2>(tb, o0, V2{v.x, -v.y});
+    st<V2>(tb, o1, V2{v.z, -v.w});
   }
 };
 
-// The one-qubit pass on complex64 storage in the pair layout; groups on the
-// diagonal of the reduced grid take the block layout (same step count).
-template <int C, int FORM, int MODE>
+// The conjugation pass on complex64 storage in the pair layout, JP pairs
+// per lane and step; groups on the diagonal of the reduced grid take the
+// block layout with 2 JP blocks per step (the same step count).  k = 1
+// holds pairs as FP64 values (as the block layout does for tile-selecting
+// targets), k = 2 as stored (16 entries per block, one block in FP64 at a
+// time).
+template <int K, int C, int FORM, int MODE, int JP>
 __global__ void __launch_bounds__(256)
-    pair_kernel(float2* __restrict__ h, ConjGeom<1, C> g, Coef<1, FORM> cf, int order) {
+    pair_kernel(float2* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf, int order) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  const DirectMem<float, MODE, true> mem{h};
-  const PairMem<MODE> pm{h};
-  constexpr int JU = 4, JP = 2;  // blocks / pairs per lane and step: 16 entries either way
+  const DirectMem<float, MODE, K == 1> mem{h};
+  const PairMem<MODE, K == 2> pm{h};
+  static_assert(K == 1 || FORM == 0, "two-qubit pair passes take the direct form");
+  constexpr int JU = 2 * JP;
   if (order == 0) {
     for (uint64_t grp = wave; grp < g.ngroups; grp += nwaves) {
       GroupCtx<C> gc;
-      group_ctx<1, C>(grp, g, gc);
+      group_ctx<K, C>(grp, g, gc);
       if (gc.diag)
-        conj_group_lane<JU, 1, C, FORM>(mem, g, gc, cf, lane);
+        conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane);
       else
-        pair_group_lane<JP, C, FORM>(pm, g, gc, cf, lane, 0, 0xffffffffu);
+        pair_group_lane<JP, K, C, FORM>(pm, g, gc, cf, lane, 0, 0xffffffffu);
     }
   } else {
     const uint32_t steps = g.jobs / JU;  // = pair_jobs / JP, a power of two
@@ -128,12 +168,12 @@ __global__ void __launch_bounds__(256)
     const uint64_t items = g.ngroups << sl;
     for (uint64_t it = wave; it < items; it += nwaves) {
       GroupCtx<C> gc;
-      group_ctx<1, C>(it >> sl, g, gc);
+      group_ctx<K, C>(it >> sl, g, gc);
       const uint32_t st = (uint32_t)(it & (steps - 1));
       if (gc.diag)
-        conj_group_lane<JU, 1, C, FORM>(mem, g, gc, cf, lane, st * JU, st * JU + JU);
+        conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane, st * JU, st * JU + JU);
       else
-        pair_group_lane<JP, C, FORM>(pm, g, gc, cf, lane, st * JP, st * JP + JP);
+        pair_group_lane<JP, K, C, FORM>(pm, g, gc, cf, lane, st * JP, st * JP + JP);
     }
   }
 }
@@ -161,23 +201,28 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
-  if constexpr (sizeof(T) == 4 && K == 1) {
-    // The pair layout needs a free column bit 0 and F >= 4.  Automatic use
-    // (pairs == 1) is limited to the targets where it measured faster at
-    // n = 16: intra targets at bit 4 or above, and cross targets below the
-    // top tile bit (intra targets 1..3 split the 16-byte accesses of a lane
-    // row across lines; at the top tile bit the block layout stays ahead).
-    const bool applies = g.F >= 4 && (C == 1 || g.ipos[0] != 0);
-    const bool pays = C == 1 ? g.cpos[0] < n - g.m - 1 : g.ipos[0] >= 4;
+  if constexpr (sizeof(T) == 4 && (K == 1 || FORM == 0)) {
+    // The pair layout (k = 1, and k = 2 in the direct form) needs a free
+    // column bit 0 and F >= 4.  Automatic use (pairs == 1) is limited to
+    // where it measured faster: every tile-selecting target set, and an
+    // intra target at bit 4 or above (intra targets 1..3 split the 16-byte
+    // accesses of a lane row across lines).  The k = 2 transfer form stays
+    // in the block layout: at 128 FP64 flops per 16 bytes of complex64
+    // traffic it is near the FP64 ridge, and pairs re-read its 16 x 16
+    // matrix once per block.
+    constexpr int KI = K - C;
+    const bool applies = g.F >= 4 && (KI == 0 || g.ipos[0] != 0);
+    const bool pays = KI == 0 || g.ipos[0] >= 4;
     if (applies && (tuning().pairs == 2 || (tuning().pairs == 1 && pays))) {
-      // 16-byte accesses in direct tiles cover whole lines: nontemporal
+      // 16-byte accesses in stored tiles cover whole lines: nontemporal
       const int pmode = tuning().mem_mode < 0 ? 3 : tuning().mem_mode;
+      constexpr int JP = K == 1 ? 2 : 1;  // 16 entries per lane and step either way
       const dim3 grid((unsigned)wgs), block(threads);
       switch (pmode) {
-        case 1: hipLaunchKernelGGL((pair_kernel<C, FORM, 1>), grid, block, 0, s, hp, g, cf, order); break;
-        case 2: hipLaunchKernelGGL((pair_kernel<C, FORM, 2>), grid, block, 0, s, hp, g, cf, order); break;
-        case 3: hipLaunchKernelGGL((pair_kernel<C, FORM, 3>), grid, block, 0, s, hp, g, cf, order); break;
-        default: hipLaunchKernelGGL((pair_kernel<C, FORM, 0>), grid, block, 0, s, hp, g, cf, order);
+        case 1: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 1, JP>), grid, block, 0, s, hp, g, cf, order); break;
+        case 2: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 2, JP>), grid, block, 0, s, hp, g, cf, order); break;
+        case 3: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 3, JP>), grid, block, 0, s, hp, g, cf, order); break;
+        default: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 0, JP>), grid, block, 0, s, hp, g, cf, order);
       }
       return hipGetLastError();
     }

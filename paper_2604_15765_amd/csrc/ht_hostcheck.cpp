@@ -50,17 +50,30 @@ struct CheckedMem {
     if (wc) wc[e]++;
     ht::store_c<double>(h + tb, off, v);
   }
-  // the pair layout's 16-byte accesses (ht_pair.h): entries off and off + 1;
-  // the GPU's accesses are 16-byte aligned, so off must be even
-  void load_pair(uint64_t tb, uint32_t off, ht::cd& a, ht::cd& b) const {
+  // the pair layout's accesses (ht_pair.h): a pair held as loaded (mirrored
+  // entries conjugated when widened, as the GPU's narrow pairs are); the
+  // GPU's 16-byte accesses are aligned, so off must be even
+  struct H {
+    ht::cd a, b;
+  };
+  H load_pair(uint64_t tb, uint32_t off) const {
     if (off & 1u) *oob = true;
-    a = load(tb, off);
-    b = load(tb, off + 1u);
+    return {load(tb, off), load(tb, off + 1u)};
   }
-  void store_pair(uint64_t tb, uint32_t off, ht::cd a, ht::cd b) const {
+  H load_two(uint64_t tb, uint32_t o0, uint32_t o1) const { return {load(tb, o0), load(tb, o1)}; }
+  static void widen(const H& x, bool cj, ht::cd& a, ht::cd& b) {
+    a = cj ? ht::conjg(x.a) : x.a;
+    b = cj ? ht::conjg(x.b) : x.b;
+  }
+  static void set(H& x, int i, ht::cd w) { (i == 0 ? x.a : x.b) = w; }
+  void store_pair(uint64_t tb, uint32_t off, const H& x) const {
     if (off & 1u) *oob = true;
-    store(tb, off, a);
-    store(tb, off + 1u, b);
+    store(tb, off, x.a);
+    store(tb, off + 1u, x.b);
+  }
+  void store_two_cj(uint64_t tb, uint32_t o0, uint32_t o1, const H& x) const {
+    store(tb, o0, ht::conjg(x.a));
+    store(tb, o1, ht::conjg(x.b));
   }
 };
 
@@ -74,21 +87,23 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
   } else {
     for (int i = 0; i < 2 * ht::Coef<K, FORM>::NE; ++i) cf.c[i] = op.coef[i];
   }
-  // the pair layout of complex64 one-qubit passes, indexing checked on this
-  // complex128 copy (the same entries, in pairs)
+  // the pair layout of complex64 passes (k = 1, and k = 2 in the direct
+  // form), indexing checked on this complex128 copy (the same entries, in
+  // pairs); JP pairs per step as on the GPU
+  constexpr int JP = K == 1 ? 2 : 1;
   bool use_pairs = false;
-  if constexpr (K == 1) use_pairs = pairs && g.F >= 4 && (C == 1 || g.ipos[0] != 0);
+  if constexpr (K == 1 || (K == 2 && FORM == 0)) use_pairs = pairs && g.F >= 4 && (K == C || g.ipos[0] != 0);
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
     ht::GroupCtx<C> gc;
     ht::group_ctx<K, C>(grp, g, gc);
-    if constexpr (K == 1) {
+    if constexpr (K <= 2) {
       if (use_pairs && !gc.diag) {
         for (uint32_t lane = 0; lane < 64; ++lane) {
           if (order == 0) {
-            ht::pair_group_lane<2, C, FORM>(mem, g, gc, cf, lane, 0, 0xffffffffu);
+            ht::pair_group_lane<JP, K, C, FORM>(mem, g, gc, cf, lane, 0, 0xffffffffu);
           } else {
-            for (uint32_t j0 = 0; j0 < ht::pair_jobs(g.F); j0 += 2)
-              ht::pair_group_lane<2, C, FORM>(mem, g, gc, cf, lane, j0, j0 + 2);
+            for (uint32_t j0 = 0; j0 < ht::pair_jobs(g.F); j0 += JP)
+              ht::pair_group_lane<JP, K, C, FORM>(mem, g, gc, cf, lane, j0, j0 + JP);
           }
           ++*lanes_run;
         }
@@ -190,7 +205,7 @@ extern "C" {
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
 // ranges of the flattened work order.  ilv: the alternating
 // patch order (lane_block).  pairs: the pair layout of complex64
-// one-qubit passes (ht_pair.h), checked on this complex128 copy.  native: allow the
+// passes (ht_pair.h) wherever it applies, checked on this complex128 copy.  native: allow the
 // native pass for permutation-and-phase operations; *form (if not NULL)
 // receives the form used.  Returns 0 on success, 1 on invalid op, 2 on an
 // out-of-range access.  *lanes_run receives the number of lane bodies run.

@@ -28,7 +28,7 @@ struct LaunchTuning {
                             // patches; -1: 1 when there are fewer groups than the grid's waves
   int native = 1;           // native pass: 0 never, 1 on operators beyond the cache, 2 always
   int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
-  int pairs = 1;            // pair layout of complex64 one-qubit passes (ht_pair.h): 0 off,
+  int pairs = 1;            // pair layout of complex64 passes (ht_pair.h): 0 off,
                             // 1 where it pays, 2 wherever it applies
 };
 LaunchTuning& tuning();

@@ -432,31 +432,35 @@ def test_c64_single_ops_within_one_rounding(ht, m):
 
 
 def test_c64_pair_layout_is_bitwise_equal_to_the_block_layout(ht):
-    """The pair layout of complex64 one-qubit passes (two blocks in adjacent
-    columns per lane, 16-byte accesses) applies the same FP64 arithmetic to
-    every block as the block layout: bitwise equal storage for every target
-    it applies to, both work orders, unitaries and channels, and within one
-    rounding of the oracle."""
+    """The pair layout of complex64 passes (two blocks in adjacent columns
+    per lane, 16-byte accesses) applies the same FP64 arithmetic to every
+    block as the block layout: bitwise equal storage for every target set
+    it applies to (one-qubit unitaries and channels, two-qubit unitaries),
+    both work orders, and within one rounding of the oracle."""
     rng = synth.make_rng(720)
     n = 9
     H = synth.random_hermitian_dense(n, rng)
     Hq = lower_hermitian(quantise_c64(H))
+    cases = []
+    for a in range(1, n):
+        cases += [([a], synth.haar_unitary(2, rng)[None]), ([a], synth.random_kraus_set(1, 3, rng))]
+    for a, b in ([5, 6], [8, 7], [6, 8], [1, 7], [4, 8], [7, 2], [3, 6], [8, 5]):
+        cases.append(([a, b], synth.haar_unitary(4, rng)[None]))
     try:
         for m in (5, 6):
-            for a in range(1, n):
-                for kraus in (synth.haar_unitary(2, rng)[None], synth.random_kraus_set(1, 3, rng)):
-                    out = []
-                    for pairs, order in ((0, 0), (2, 0), (2, 1)):
-                        ht.set_tuning("pairs", pairs)
-                        ht.set_tuning("conj_order", order)
-                        h = make(ht, n, m, H, dtype="c64")
-                        h.apply_channel([a], kraus)
-                        out.append((h.raw_entries(), h.to_dense()))
-                        h.close()
-                    assert np.array_equal(out[0][0], out[1][0]), (m, a)
-                    assert np.array_equal(out[0][0], out[2][0]), (m, a)
-                    e = rel(out[1][1], oracle.kraus_map(Hq, kraus, [a]))
-                    assert e <= 2 * C64_EPS, (m, a, e)
+            for targets, kraus in cases:
+                out = []
+                for pairs, order in ((0, 0), (2, 0), (2, 1)):
+                    ht.set_tuning("pairs", pairs)
+                    ht.set_tuning("conj_order", order)
+                    h = make(ht, n, m, H, dtype="c64")
+                    h.apply_channel(targets, kraus)
+                    out.append((h.raw_entries(), h.to_dense()))
+                    h.close()
+                assert np.array_equal(out[0][0], out[1][0]), (m, targets)
+                assert np.array_equal(out[0][0], out[2][0]), (m, targets)
+                e = rel(out[1][1], oracle.kraus_map(Hq, kraus, targets))
+                assert e <= 2 * C64_EPS, (m, targets, e)
     finally:
         ht.set_tuning("pairs", 1)
         ht.set_tuning("conj_order", -1)

@@ -275,7 +275,7 @@ def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
         assert form in (0, 1), (t, form)
 
 
-# ------------------------------------------- pair layout (complex64, k = 1)
+# -------------------------------------- pair layout (complex64, k = 1, 2)
 
 @pytest.mark.parametrize("m", [4, 5, 6])
 def test_pair_layout_covers_every_entry_once(hc, m):
@@ -296,6 +296,31 @@ def test_pair_layout_covers_every_entry_once(hc, m):
                 b, _ = emulate(hc, raw, n, m, [a], kraus, heis, order, pairs=0)
                 assert np.all(wp == 1), (n, m, a, np.unique(wp))
                 assert np.array_equal(p, b), (n, m, a)
+
+
+@pytest.mark.parametrize("m", [4, 5])
+def test_pair_layout_two_qubit_ops(hc, m):
+    """The pair layout of complex64 two-qubit passes in the direct form (16
+    entries per block, pairs held as loaded and transformed one block at a
+    time): every entry read and written once, results those of the block
+    layout, on every ordered pair of targets (the layout applies where both
+    targets select tiles, or the intra one is above bit 0 and 4 free bits
+    remain; channels take the block layout)."""
+    rng = synth.make_rng(1400 + m)
+    n = m + 2
+    H = synth.random_hermitian_dense(n, rng)
+    raw = layout.encode(H, m)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            kraus = synth.haar_unitary(4, rng)[None] if rng.random() < 0.8 else synth.random_kraus_set(2, 3, rng)
+            heis = bool(rng.integers(2))
+            order = int(rng.integers(2))
+            p, wp = emulate(hc, raw, n, m, [a, b], kraus, heis, order, pairs=1)
+            q, _ = emulate(hc, raw, n, m, [a, b], kraus, heis, order, pairs=0)
+            assert np.all(wp == 1), (n, m, a, b, np.unique(wp))
+            assert np.array_equal(p, q), (n, m, a, b)
 
 
 # ----------------------------------------------- k = 3 Kraus form (form 3)
