@@ -48,7 +48,7 @@ def kernel_class(name: str):
     """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct',
     'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
     'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus',
-    'pair_kernel<1, 0, 3>' -> 'c64_k1_c1_direct' (complex64 only); None
+    'pair_kernel<1, 1, 0, 3, 2>' -> 'c64_k1_c1_direct' (complex64 only); None
     otherwise."""
     m = re.search(r"conj_kernel<(double|float), (\d), (\d), (\d), (\d)>", name)
     if m:
@@ -62,9 +62,9 @@ def kernel_class(name: str):
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k3_c{m.group(2)}_kraus"
-    m = re.search(r"pair_kernel<(\d), (\d), (\d)>", name)
+    m = re.search(r"pair_kernel<(\d), (\d), (\d), (\d), (\d)>", name)
     if m:
-        return f"c64_k1_c{m.group(1)}_{'direct' if m.group(2) == '0' else 'transfer'}"
+        return f"c64_k{m.group(1)}_c{m.group(2)}_{'direct' if m.group(3) == '0' else 'transfer'}"
     return None
 
 
@@ -80,6 +80,8 @@ def main():
         p.add_argument("--" + a, required=True)
     p.add_argument("--copy-bytes", type=float, default=34376515584.0,
                    help="bytes the copy kernel reads (and writes) per launch")
+    p.add_argument("--title", default="conjugation passes of the n = 16 complex128 layered benchmark",
+                   help="what the profiled command ran")
     args = p.parse_args()
 
     stats = _csv(args.stats, "kernel_stats.csv")
@@ -94,7 +96,7 @@ def main():
     kw = args.copy_bytes / w_copy
 
     lines = [
-        "# rocprofv3 summary: conjugation passes of the n = 16 complex128 layered benchmark",
+        f"# rocprofv3 summary: {args.title}",
         f"# kernel source fingerprint: {source_fingerprint()}",
         "# commands (from the repository root; rocprofv3 run from /tmp with absolute paths):",
     ]

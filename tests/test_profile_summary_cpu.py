@@ -11,8 +11,9 @@ def test_kernel_class():
         "ht::native_kernel<double, 1, 0, 3, 16, 0>": "c128_k1_c0_native",
         "ht::native_kernel<float, 3, 2, 0, 32, 1>": "c64_k3_c2_native",
         "ht::k3_kernel<double, 1, 3>": "c128_k3_c1_kraus",
-        "ht::pair_kernel<1, 0, 3>": "c64_k1_c1_direct",
-        "ht::pair_kernel<0, 1, 0>": "c64_k1_c0_transfer",
+        "ht::pair_kernel<1, 1, 0, 3, 2>": "c64_k1_c1_direct",
+        "ht::pair_kernel<1, 0, 1, 0, 2>": "c64_k1_c0_transfer",
+        "ht::pair_kernel<2, 2, 0, 3, 1>": "c64_k2_c2_direct",
         "ht::trace_partial_kernel<double>": None,
         "ht::batch_kernel<float>": None,
     }
