@@ -322,15 +322,19 @@ def _sampled_op_check(h, op, picture, n, rng, nblocks=1500):
     return rel(after, want)
 
 
-@pytest.mark.parametrize("n", [14, 16])
-def test_full_size_sampled_blocks(ht, n):
-    """Full-size operators (n = 14: 2.15 GB, n = 16: 34.4 GB of c128 tiles,
-    tile edge 32, the benchmark's launch configuration): every op class at
-    intra and cross positions, checked on 1500 sampled blocks per op, plus
-    trace preservation over the whole operator."""
-    rng = synth.make_rng(900 + n)
+@pytest.mark.parametrize("n,dtype", [(14, "c128"), (16, "c128"), (16, "c64")])
+def test_full_size_sampled_blocks(ht, n, dtype):
+    """Full-size operators (n = 14: 2.15 GB, n = 16: 34.4 GB of c128 tiles or
+    17.2 GB of c64, tile edge 32, the benchmark's launch configuration):
+    every op class at intra and cross positions, checked on 1500 sampled
+    blocks per op, plus trace preservation over the whole operator.  In
+    complex64 the extra ops take the pair layout in both of its memory modes
+    (nontemporal, and plain where the highest target is at n - 3 or above);
+    each result lies within one float rounding of the FP64 map of its
+    stored input."""
+    rng = synth.make_rng(900 + n + (7 if dtype == "c64" else 0))
     G = synth.ginibre_factor(n, 16, rng)
-    h = ht.Herm(n, 5)
+    h = ht.Herm(n, 5, dtype)
     h.init_lowrank(G)
     h.scale(1.0 / h.trace())
     ops = [
@@ -345,11 +349,22 @@ def test_full_size_sampled_blocks(ht, n):
         synth.random_ops.channel_op([7, 12], synth.random_kraus_set(2, 3, rng)),     # k=2 c=2 transfer
         synth.random_ops.unitary_op([0, n - 2], synth.cnot_matrix()),                # k=2 c=1
     ]
+    if dtype == "c64":
+        ops += [
+            synth.random_ops.unitary_op([4], synth.haar_unitary(2, rng)),             # pairs, intra bit 4
+            synth.random_ops.channel_op([10], synth.amplitude_damping_kraus(0.05)),   # pairs, transfer
+            synth.random_ops.unitary_op([n - 2], synth.haar_unitary(2, rng)),         # pairs, plain
+            synth.random_ops.unitary_op([9, 10], synth.haar_unitary(4, rng)),         # k=2 pairs
+            synth.random_ops.unitary_op([n - 1, n - 2], synth.haar_unitary(4, rng)),  # k=2 pairs, plain
+            synth.random_ops.unitary_op([10, 4], synth.haar_unitary(4, rng)),         # k=2 pairs, intra 4
+        ]
+    tol = TOL if dtype == "c128" else 2 * C64_EPS
     for i, op in enumerate(ops):
         pic = i % 2 if op.kind == "unitary" else 0
         e = _sampled_op_check(h, op, pic, n, rng)
-        assert e <= TOL, (op.label, op.targets, e)
-    assert abs(h.trace() - 1.0) < 1e-12
+        assert e <= tol, (op.label, op.targets, e)
+    assert abs(h.trace() - 1.0) < (1e-12 if dtype == "c128" else 1e-6)
+    h.close()
 
 
 def test_largest_operator(ht):
