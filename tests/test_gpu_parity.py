@@ -451,7 +451,9 @@ def test_c64_pair_layout_is_bitwise_equal_to_the_block_layout(ht):
     per lane, 16-byte accesses) applies the same FP64 arithmetic to every
     block as the block layout: bitwise equal storage for every target set
     it applies to (one-qubit unitaries and channels, two-qubit unitaries),
-    both work orders, and within one rounding of the oracle."""
+    both work orders, both pictures, both memory modes of the automatic
+    choice (targets at n - 3 and above, and below), and within one rounding
+    of the oracle."""
     rng = synth.make_rng(720)
     n = 9
     H = synth.random_hermitian_dense(n, rng)
@@ -463,19 +465,21 @@ def test_c64_pair_layout_is_bitwise_equal_to_the_block_layout(ht):
         cases.append(([a, b], synth.haar_unitary(4, rng)[None]))
     try:
         for m in (5, 6):
-            for targets, kraus in cases:
+            for i, (targets, kraus) in enumerate(cases):
+                pic = (i + m) % 2
                 out = []
                 for pairs, order in ((0, 0), (2, 0), (2, 1)):
                     ht.set_tuning("pairs", pairs)
                     ht.set_tuning("conj_order", order)
                     h = make(ht, n, m, H, dtype="c64")
-                    h.apply_channel(targets, kraus)
+                    h.apply_channel(targets, kraus, pic)
                     out.append((h.raw_entries(), h.to_dense()))
                     h.close()
-                assert np.array_equal(out[0][0], out[1][0]), (m, targets)
-                assert np.array_equal(out[0][0], out[2][0]), (m, targets)
-                e = rel(out[1][1], oracle.kraus_map(Hq, kraus, targets))
-                assert e <= 2 * C64_EPS, (m, targets, e)
+                assert np.array_equal(out[0][0], out[1][0]), (m, targets, pic)
+                assert np.array_equal(out[0][0], out[2][0]), (m, targets, pic)
+                ref = (oracle.kraus_map_adjoint if pic else oracle.kraus_map)(Hq, kraus, targets)
+                e = rel(out[1][1], ref)
+                assert e <= 2 * C64_EPS, (m, targets, pic, e)
     finally:
         ht.set_tuning("pairs", 1)
         ht.set_tuning("conj_order", -1)
