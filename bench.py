@@ -14,8 +14,10 @@ over the K timed steps; ``roofline`` = algorithmic bytes (every stored entry
 read and written once per pass) / measured time of the kernel class that takes
 the most time, against MI355X's 8 TB/s; ``cpu_baseline`` = the CPU oracle
 (Eq. (2) block form, numpy) on a bounded sample, see ``cpu_baseline()``;
-``fused`` = the same steps from the same state with each layer run as a
-fused circuit (ops grouped into 2-qubit passes), see ``fused_run()``.
+``complex64`` = the same steps from the same state in complex64 storage
+(FP64 arithmetic), see ``c64_run()``; ``fused`` = the same steps from the
+same state with each layer run as a fused circuit (ops grouped into 2-qubit
+passes), see ``fused_run()``.
 ``value`` is the op-by-op figure: one pass per op, as the method defines.
 ``serving`` = the metric's served half: circuits/s and p50/p99 latency of a
 Poisson request stream under continuous batching (and with each request's
@@ -49,6 +51,8 @@ def parse():
     p.add_argument("--seed", type=int, default=1616)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fused", action="store_true", help="skip the fused-circuit run of the same steps")
+    p.add_argument("--no-c64", action="store_true",
+                   help="skip the complex64-storage run of the same steps (run only with --dtype c128)")
     p.add_argument("--no-serve", action="store_true", help="skip the served-requests run")
     p.add_argument("--serve-count", type=int, default=48, help="requests of the served-requests run")
     p.add_argument("--serve-rate", type=float, default=1000.0, help="Poisson arrival rate (/s) of that run")
@@ -107,6 +111,49 @@ def cpu_baseline(n_full: int, n_sample: int, seed: int) -> dict:
                    f"per-op time scaled by 4^{n_full - n_sample} to n={n_full}"),
         "seconds": dt,
     }
+
+
+def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128) -> dict:
+    """The same steps from the same initial state in complex64 storage (FP64
+    arithmetic and reductions, the pair layout where it applies): its own
+    passes/s and HBM rate, and how far its readouts are from the complex128
+    run's after the same steps."""
+    import torch
+    h = ht.Herm(args.n, args.tile_log2, "c64")
+    h.init_lowrank(G)
+    h.scale(1.0 / h.trace())
+    for l in range(args.warmup):
+        for op in layers[l]:
+            h.apply_op(op)
+    h.profile_reset()
+    h.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nops = 0
+    for l in range(args.warmup, args.warmup + args.steps):
+        for op in layers[l]:
+            h.apply_op(op)
+        nops += len(layers[l])
+        tr, ev = h.trace(), h.expectation_pauli_sum(codes, coeffs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile_enable(False)
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    out = {
+        "value": nops / elapsed,
+        "unit": "gate-conj/s",
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "storage_bytes": h.nbytes,
+        "hbm_GBps": nops * 2.0 * h.nbytes / elapsed / 1e9,
+        "dominant_class": dom_name,
+        "dominant_GBps": dom["bytes"] / (dom["ms"] * 1e-3) / 1e9,
+        "trace_diff_vs_c128": abs(tr - tr_c128),
+        "pauli_expectation_diff_vs_c128": abs(ev - ev_c128),
+    }
+    h.close()
+    log(f"[bench] complex64: {out['value']:.1f} gate-conj/s, {out['hbm_GBps']:.0f} GB/s")
+    return out
 
 
 def fused_run(ht, h, G, layers, args, codes, coeffs, tr_plain, ev_plain) -> dict:
@@ -329,6 +376,8 @@ def main():
         "final_trace": tr,
         "final_pauli_expectation": ev,
     }
+    if args.dtype == "c128" and not args.no_c64:
+        out["complex64"] = c64_run(ht, G, layers, args, codes, coeffs, tr, ev)
     if not args.no_fused:
         out["fused"] = fused_run(ht, h, G, layers, args, codes, coeffs, tr, ev)
     if not args.no_serve:
