@@ -464,7 +464,7 @@ def test_c64_pair_layout_is_bitwise_equal_to_the_block_layout(ht):
     for a, b in ([5, 6], [8, 7], [6, 8], [1, 7], [4, 8], [7, 2], [3, 6], [8, 5]):
         cases.append(([a, b], synth.haar_unitary(4, rng)[None]))
     try:
-        for m in (5, 6):
+        for m in (5, 6, 7, 8):
             for i, (targets, kraus) in enumerate(cases):
                 pic = (i + m) % 2
                 out = []

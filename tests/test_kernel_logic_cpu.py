@@ -277,7 +277,7 @@ def test_native_is_chosen_only_for_permutation_and_phase_ops(hc):
 
 # -------------------------------------- pair layout (complex64, k = 1, 2)
 
-@pytest.mark.parametrize("m", [4, 5, 6])
+@pytest.mark.parametrize("m", [4, 5, 6, 7])
 def test_pair_layout_covers_every_entry_once(hc, m):
     """The pair layout of complex64 one-qubit passes (two blocks in adjacent
     columns per lane, 16-byte accesses in stored tiles): every entry read and
@@ -298,7 +298,7 @@ def test_pair_layout_covers_every_entry_once(hc, m):
                 assert np.array_equal(p, b), (n, m, a)
 
 
-@pytest.mark.parametrize("m", [4, 5])
+@pytest.mark.parametrize("m", [4, 5, 6])
 def test_pair_layout_two_qubit_ops(hc, m):
     """The pair layout of complex64 two-qubit passes in the direct form (16
     entries per block, pairs held as loaded and transformed one block at a
