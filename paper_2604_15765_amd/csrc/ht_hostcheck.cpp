@@ -144,16 +144,10 @@ void run_k3(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, uint6
       }
       for (int a = 0; a < op.nkraus; ++a) {
         const double* Aa = op.coef + 128 * a;
-        for (uint32_t lane = 0; lane < 64; ++lane) {
-          ht::cd t[8];
-          ht::k3_left(Aa, x[lane], t);
-          for (int u = 0; u < 8; ++u) table[lane >> 3][u][lane & 7] = t[u];
-        }
-        for (uint32_t lane = 0; lane < 64; ++lane) {
-          ht::cd t[8];
-          for (int l = 0; l < 8; ++l) t[l] = table[lane >> 3][lane & 7][l];
-          ht::k3_right_acc(Aa, t, w[lane]);
-        }
+        for (uint32_t lane = 0; lane < 64; ++lane)
+          ht::k3_left(Aa, x[lane], [&](int u, ht::cd t) { table[lane >> 3][u][lane & 7] = t; });
+        for (uint32_t lane = 0; lane < 64; ++lane)
+          ht::k3_right_acc(Aa, [&](int l) { return table[lane >> 3][lane & 7][l]; }, w[lane]);
       }
       for (uint32_t lane = 0; lane < 64; ++lane)
         if (bk[lane].active) ht::k3_store_row<C>(mem, g, gr, tiles[lane & 7], bk[lane], (int)(lane & 7), w[lane]);

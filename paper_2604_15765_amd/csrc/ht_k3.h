@@ -99,25 +99,35 @@ HT_HD void k3_load_col(const Mem& mem, const ConjGeom<3, C>& g, const K3Tiles<C>
   }
 }
 
-// t = A x for one column (A row-major 8 x 8, interleaved complex).
-HT_HD void k3_left(const double* __restrict__ A, const cd (&x)[8], cd (&t)[8]) {
-#pragma unroll
+// The two products of one Kraus operator (A row-major 8 x 8, interleaved
+// complex).  Both loop over rows or columns of A without unrolling the
+// outer loop: fully unrolled, the compiler hoists all 128 uniform
+// coefficient loads and spills most of them (about three register-spill
+// instructions per FP64 FMA); one row or column at a time fits.  The
+// results are exchanged through put / get rather than register arrays
+// indexed by the loop counter.
+
+// t = A x for one column: put(u, t[u]) for u = 0..7.
+template <typename Put>
+HT_HD void k3_left(const double* __restrict__ A, const cd (&x)[8], Put&& put) {
+#pragma unroll 1
   for (int u = 0; u < 8; ++u) {
     cd acc = {0.0, 0.0};
 #pragma unroll
     for (int l = 0; l < 8; ++l) acc = cfma(acc, cd{A[2 * (u * 8 + l)], A[2 * (u * 8 + l) + 1]}, x[l]);
-    t[u] = acc;
+    put(u, acc);
   }
 }
 
-// w[v] += sum_l t[l] conj(A[v][l]) for one row t of A x.
-HT_HD void k3_right_acc(const double* __restrict__ A, const cd (&t)[8], cd (&w)[8]) {
+// w[v] += sum_l t[l] conj(A[v][l]) for one row t of A x, t[l] = get(l); each
+// w[v] takes its terms in the order l = 0..7.
+template <typename Get>
+HT_HD void k3_right_acc(const double* __restrict__ A, Get&& get, cd (&w)[8]) {
+#pragma unroll 1
+  for (int l = 0; l < 8; ++l) {
+    const cd tl = get(l);
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    cd acc = w[v];
-#pragma unroll
-    for (int l = 0; l < 8; ++l) acc = cfma_cj(acc, t[l], cd{A[2 * (v * 8 + l)], A[2 * (v * 8 + l) + 1]});
-    w[v] = acc;
+    for (int v = 0; v < 8; ++v) w[v] = cfma_cj(w[v], tl, cd{A[2 * (v * 8 + l)], A[2 * (v * 8 + l) + 1]});
   }
 }
 

@@ -50,18 +50,13 @@ __global__ void __launch_bounds__(kK3Threads)
       for (int v = 0; v < 8; ++v) w[v] = cd{0.0, 0.0};
       for (int a = 0; a < nkraus; ++a) {
         const double* Aa = A + 128 * a;
-        cd t[8];
-        k3_left(Aa, x, t);
         wave_lds_sync();  // the previous operator's reads of this slot are done
-#pragma unroll
-        for (int u = 0; u < 8; ++u) slot[u * kK3Pad + j] = make_double2(t[u].re, t[u].im);
+        k3_left(Aa, x, [&](int u, cd t) { slot[u * kK3Pad + j] = make_double2(t.re, t.im); });
         wave_lds_sync();
-#pragma unroll
-        for (int l = 0; l < 8; ++l) {
+        k3_right_acc(Aa, [&](int l) {
           const double2 v = slot[j * kK3Pad + l];
-          t[l] = cd{v.x, v.y};
-        }
-        k3_right_acc(Aa, t, w);
+          return cd{v.x, v.y};
+        }, w);
       }
       if (bk.active) k3_store_row<C>(mem, g, gr, tiles, bk, j, w);
       wave_lds_sync();
