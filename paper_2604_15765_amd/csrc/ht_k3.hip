@@ -73,12 +73,15 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   uint64_t wgs = (g.ngroups + waves_per_wg - 1) / waves_per_wg;
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
+  // Automatic mode: plain loads and stores.  The 8 lanes of a block run down
+  // the columns of a mirrored tile, so its lines are read in 16-byte pieces
+  // by different steps; a nontemporal load lets a line go after its first
+  // piece and the rest are fetched again (measured at n = 16, complex128:
+  // 2.8x the algorithmic read bytes with all three targets tile-selecting,
+  // +20 % with one or two).  With no mirrored tile the hint measured no
+  // better either.
   int mode = tuning().mem_mode;
-  if (mode < 0) {
-    // nontemporal only where every store covers whole 128-byte lines
-    constexpr int KI = 3 - C;
-    mode = (sizeof(T) == 8 && (KI == 0 || g.ipos[0] >= 3)) ? 3 : 0;
-  }
+  if (mode < 0) mode = 0;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
   const dim3 grid((unsigned)wgs), block(kK3Threads);
   if (mode == 3)
