@@ -65,9 +65,12 @@ struct K3Block {
   bool active;
 };
 
-// Block b of a group (b < 4^F active): base row from b's high F bits, base
-// column from its low F bits, so blocks 8 s .. 8 s + 7 share a row and have
-// consecutive free columns.
+// Block b of a group (b < 4^F active).  The 8 blocks of a step (b >> 3)
+// share a base row and have 8 consecutive free columns, so a stored tile is
+// read in rows of 8 entries.  Consecutive steps advance the row first
+// (F >= 3): in a mirrored tile, where those 8 blocks run down a column, the
+// lines one step reads in 16-byte pieces are read again by the next steps
+// while they are still cached.
 template <int C>
 HT_HD K3Block k3_block(const ConjGeom<3, C>& g, const K3Group& gr, uint32_t b) {
   constexpr int KI = 3 - C;
@@ -76,8 +79,16 @@ HT_HD K3Block k3_block(const ConjGeom<3, C>& g, const K3Group& gr, uint32_t b) {
   K3Block r;
   r.active = b < nblk;
   if (!r.active) b = 0;
-  r.p = deposit_free<KI>(b >> g.F, g.ipos);
-  r.q = deposit_free<KI>(b & fm, g.ipos);
+  uint32_t pi, qi;
+  if (g.F >= 3) {
+    pi = (b >> 3) & fm;
+    qi = ((b >> (3 + g.F)) << 3) | (b & 7u);
+  } else {
+    pi = b >> g.F;
+    qi = b & fm;
+  }
+  r.p = deposit_free<KI>(pi, g.ipos);
+  r.q = deposit_free<KI>(qi, g.ipos);
   r.active = r.active && !(gr.diag && r.p < r.q);
   return r;
 }
