@@ -69,7 +69,19 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
                            int num_cu, hipStream_t s) {
   const ConjGeom<3, C> g = make_geom<3, C>(n, m, op.sorted, false);
   const uint64_t waves_per_wg = kK3Threads / 64;
-  const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
+  // Workgroups per compute unit: for a single complex128 operator (memory
+  // bound) fewer than the conjugation pass uses, as measured at n = 16: 1
+  // when a group is one tile split into two steps (F <= 2), else 2.  Fewer
+  // waves in flight leave more L2 per wave for the partial lines this pass
+  // reads and writes (targets [0, 1, 2]: 21.0 -> 16.0 ms).  Channels (FP64
+  // bound) and complex64 keep the tuning value: there fewer waves measured
+  // slower.
+  uint64_t per_cu = (uint64_t)tuning().wg_per_cu;
+  if (sizeof(T) == 8 && op.nkraus == 1) {
+    const uint64_t k3_cap = g.F <= 2 ? 1 : 2;
+    if (per_cu > k3_cap) per_cu = k3_cap;
+  }
+  const uint64_t cap = (uint64_t)num_cu * per_cu;
   uint64_t wgs = (g.ngroups + waves_per_wg - 1) / waves_per_wg;
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
