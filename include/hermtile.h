@@ -465,8 +465,11 @@ ht_status ht_profile_reset(ht_herm* h);
 const char* ht_kernel_class_name(int idx);
 
 /* Launch tuning of the conjugation pass, process-wide; it changes speed, never
- * results.  "conj_wg_per_cu" (1..64, default 8): workgroups per compute unit
- * of the grid-stride grid.  "conj_block_threads" (64, 128 or 256, default
+ * results.  "conj_wg_per_cu" (-1 or 1..64, default -1): workgroups per
+ * compute unit of the grid-stride grid; -1 = automatic: 2 for the complex128
+ * conjugation pass on operators of 1 GiB and more, 8 for smaller ones, complex64, the native pass and the three-qubit
+ * Kraus-form pass (which itself caps single-operator complex128 passes at 2,
+ * or 1 when a group is one tile).  "conj_block_threads" (64, 128 or 256, default
  * 256): workgroup size.  "conj_mem_mode" (-1..3, default -1 = automatic:
  * nontemporal loads and stores when every store writes whole cache lines);
  * 0..3: bit 0 marks the pass's loads nontemporal, bit 1 its stores.  "conj_order" (-1, 0 or 1,

@@ -588,7 +588,8 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
   if (!name) return ht_fail(HT_EINVAL, "name is NULL");
   const std::string k(name);
   if (k == "conj_wg_per_cu") {
-    if (value < 1 || value > 64) return ht_fail(HT_EINVAL, "conj_wg_per_cu must be in [1, 64]");
+    if (value != -1 && (value < 1 || value > 64))
+      return ht_fail(HT_EINVAL, "conj_wg_per_cu must be -1 (automatic) or in [1, 64]");
     ht::tuning().wg_per_cu = (int)value;
     return HT_OK;
   }

@@ -22,7 +22,8 @@ inline int conj_class(int k, int c, int form) {
 
 struct LaunchTuning {
   int block_threads = 256;  // 4 waves per workgroup
-  int wg_per_cu = 8;        // cap on resident workgroups per CU of the grid-stride grid
+  int wg_per_cu = -1;       // cap on resident workgroups per CU of the grid-stride grid;
+                            // -1: automatic (wg_per_cu_or below)
   int mem_mode = -1;        // -1: automatic; else bit 0: nontemporal loads, bit 1: stores
   int order = -1;           // 0: a wave walks a whole group; 1: waves share a group's
                             // patches; -1: 1 when there are fewer groups than the grid's waves
@@ -32,6 +33,13 @@ struct LaunchTuning {
                             // 1 where it pays, 2 wherever it applies
 };
 LaunchTuning& tuning();
+
+// Workgroups per CU for a kernel family: the tuning value if set, else the
+// family's measured default auto_value.
+inline int wg_per_cu_or(int auto_value) {
+  return tuning().wg_per_cu > 0 ? tuning().wg_per_cu : auto_value;
+}
+
 // allow_native for prepare_op on an operator of `bytes` bytes: the native
 // pass only pays where the pass is bound by HBM (an operator larger than the
 // 256 MiB Infinity Cache: on cache-resident operators it measured up to 1.8x

@@ -76,7 +76,7 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   // reads and writes (targets [0, 1, 2]: 21.0 -> 16.0 ms).  Channels (FP64
   // bound) and complex64 keep the tuning value: there fewer waves measured
   // slower.
-  uint64_t per_cu = (uint64_t)tuning().wg_per_cu;
+  uint64_t per_cu = (uint64_t)wg_per_cu_or(8);
   if (sizeof(T) == 8 && op.nkraus == 1) {
     const uint64_t k3_cap = g.F <= 2 ? 1 : 2;
     if (per_cu > k3_cap) per_cu = k3_cap;

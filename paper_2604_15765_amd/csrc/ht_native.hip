@@ -59,7 +59,9 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const
   op.c = coef_dev;
   const int threads = tuning().block_threads;
   const uint64_t waves_per_wg = (uint64_t)threads / 64;
-  const uint64_t cap = (uint64_t)num_cu * (uint64_t)tuning().wg_per_cu;
+  // automatic: 8 workgroups per CU (2, as for the conjugation pass in
+  // complex128, measured 5-50 % slower here)
+  const uint64_t cap = (uint64_t)num_cu * (uint64_t)wg_per_cu_or(8);
   // work order as for the conjugation pass
   int order = tuning().order;
   if (order < 0) order = g.ngroups < cap * waves_per_wg ? 1 : 0;

@@ -179,13 +179,14 @@ def test_native_tuning_switch(ht):
 
 def test_tuning_validation(ht):
     ht.set_tuning("conj_wg_per_cu", 8)
+    ht.set_tuning("conj_wg_per_cu", -1)  # automatic, the default
     ht.set_tuning("conj_block_threads", 256)
     ht.set_tuning("interleave", 1)
     for v in (0, 1, -1):  # -1 (automatic) is the default
         ht.set_tuning("conj_order", v)
     for v in (0, 2, 1):  # 1 (where it pays) is the default
         ht.set_tuning("pairs", v)
-    for name, v in (("conj_wg_per_cu", 0), ("conj_block_threads", 100), ("nope", 1), ("interleave", 2),
+    for name, v in (("conj_wg_per_cu", 0), ("conj_wg_per_cu", -2), ("conj_block_threads", 100), ("nope", 1), ("interleave", 2),
                     ("conj_order", 2), ("conj_order", -2), ("pairs", 3), ("pairs", -1)):
         with pytest.raises(ht.HermError):
             ht.set_tuning(name, v)
