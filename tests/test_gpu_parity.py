@@ -144,7 +144,8 @@ def test_work_orders_give_bitwise_equal_results(ht):
     """Whole groups per wave (order 0) and group steps spread over waves
     (order 1, the default below one group per wave) update the same blocks
     with the same arithmetic: bitwise equal storage, generic and native
-    passes, every class."""
+    passes, every class.  So do grids of 1, 2 and 8 workgroups per CU and
+    the automatic choice."""
     rng = synth.make_rng(470)
     n = 9
     H = synth.random_hermitian_dense(n, rng)
@@ -162,16 +163,19 @@ def test_work_orders_give_bitwise_equal_results(ht):
     try:
         for m in (3, 5):
             out = []
-            for order in (0, 1):
+            for order, wg in ((0, -1), (1, -1), (0, 1), (1, 2), (0, 8)):
                 ht.set_tuning("conj_order", order)
+                ht.set_tuning("conj_wg_per_cu", wg)
                 h = make(ht, n, m, H)
                 for t, mats in ops:
                     h.apply_channel(t, mats)
                 out.append(h.raw_entries())
                 h.close()
-            assert np.array_equal(out[0], out[1]), m
+            for i in range(1, len(out)):
+                assert np.array_equal(out[0], out[i]), (m, i)
     finally:
         ht.set_tuning("conj_order", -1)
+        ht.set_tuning("conj_wg_per_cu", -1)
         ht.set_tuning("native", 1)
 
 
