@@ -466,8 +466,9 @@ const char* ht_kernel_class_name(int idx);
 
 /* Launch tuning of the conjugation pass, process-wide; it changes speed, never
  * results.  "conj_wg_per_cu" (-1 or 1..64, default -1): workgroups per
- * compute unit of the grid-stride grid; -1 = automatic: 2 for the complex128
- * conjugation pass on operators of 1 GiB and more, 8 for smaller ones, complex64, the native pass and the three-qubit
+ * compute unit of the grid-stride grid; -1 = automatic: for the complex128
+ * conjugation pass on operators of 1 GiB and more 1 (unitaries) or 2
+ * (channels), 8 for smaller ones, complex64, the native pass and the three-qubit
  * Kraus-form pass (which itself caps single-operator complex128 passes at 2,
  * or 1 when a group is one tile).  "conj_block_threads" (64, 128 or 256, default
  * 256): workgroup size.  "conj_mem_mode" (-1..3, default -1 = automatic:

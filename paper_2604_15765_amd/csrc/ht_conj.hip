@@ -191,14 +191,16 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   const int threads = tuning().block_threads;
   const uint64_t waves_per_wg = (uint64_t)threads / 64;
   const uint64_t steps = (g.jobs + conj_unroll(K, (int)sizeof(T) * 2) - 1) / conj_unroll(K, (int)sizeof(T) * 2);
-  // Automatic workgroups per CU: 2 for complex128 operators of 1 GiB and
-  // more (measured at n = 16 and 14: fewer waves in flight keep the groups
-  // being worked on close together in memory; the n = 16 layers ran 74.5
-  // passes/s against 72.8 at 8), else 8 (a cache-resident n = 12 operator
-  // ran 13 % slower at 2, and complex64 slower in the block layout)
+  // Automatic workgroups per CU for complex128 operators of 1 GiB and more:
+  // 1 in the direct form, 2 in the transfer form (measured at n = 16 and 14:
+  // fewer waves in flight keep the groups being worked on close together in
+  // memory; the n = 16 layers ran 74.9 passes/s against 72.8 at 8; one wave
+  // per SIMD cannot hide the transfer form's FP64 work).  Else 8: a
+  // cache-resident n = 12 operator ran 13 % slower at 2, and complex64
+  // slower in the block layout.
   const uint64_t nent = ((1ull << n) * ((1ull << n) + (1ull << g.m))) >> 1;
   const bool big = sizeof(T) == 8 && nent * 2 * sizeof(T) >= (1ull << 30);
-  const uint64_t cap = (uint64_t)num_cu * (uint64_t)wg_per_cu_or(big ? 2 : 8);
+  const uint64_t cap = (uint64_t)num_cu * (uint64_t)wg_per_cu_or(big ? (FORM == 0 ? 1 : 2) : 8);
   // automatic order: split groups over waves when whole groups would leave
   // the grid's waves idle (small operators, few large cross-tile groups)
   int order = tuning().order;
