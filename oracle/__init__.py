@@ -18,7 +18,34 @@ readouts    trace, tr(rho O), Pauli strings and Pauli sums.
 layout      the tiled lower-triangle format of Section III-B and Table I, the
             case analysis of Algorithm 3 and the tiled expectation formula.
 
-Every function cites the passage of the paper it follows.  Readings of
+Every function cites the passage of the paper it follows, and every one is
+pinned by a CPU test (``tests/test_oracle_pins.py``) to something other than
+itself; ``tests/test_oracle_mutations.py`` plants a plausible mistake in each
+and shows that a pin fails:
+
+    expand_local           np.kron for single targets and adjacent pairs (both
+                           orders); CNOT's action on matrix units
+    kraus_map              closed forms of Pauli conjugation, depolarising,
+                           amplitude damping, dephasing; hermiticity, trace
+                           preservation, positivity; diagonal gates and CNOT
+                           leave their fixed entries bitwise; 2x2 worked cases
+    kraus_map_adjoint      duality tr(O Phi(rho)) = tr(Phi*(O) rho), unitality
+    apply_ops(_local)      hand-derived results of two non-commuting ops
+                           (X, amplitude damping) in both pictures
+    insert_bits            digit-string construction, bijection
+    block_indices          digit-string construction for unsorted targets;
+                           the subspaces partition the index range
+    block_update           the column-stacking identity behind Eq. (3)
+    local_block_map        the Kronecker form on every target set; every
+                           gathered block equals block_update of the block
+    trace                  unitary invariance, tr I = N
+    expectation            tr(rho I) = tr rho; single Pauli strings by masks
+    pauli_string_matrix,   entry-by-entry phase/permutation closed form;
+    pauli_sum_matrix,      tr(rho O) from the bit masks alone
+    pauli_sum_expectation
+    density_from_factor    projector for one column, P/r for r orthonormal
+    layout                 Table I, round trip, Algorithm 3 case counts and
+                           tile ownership, the strict tiled expectation  Readings of
 passages that are silent or inconsistent are listed in the design notes; the
 ones that matter here are: qubit q is bit q of an index (little-endian); local
 bit l of a k-local matrix belongs to ``targets[l]``; the Heisenberg map is
@@ -31,8 +58,6 @@ from .local_block import (
     local_block_map,
     block_update,
     block_indices,
-    gather_block,
-    scatter_block,
     apply_ops_local,
 )
 from .readouts import (
@@ -54,8 +79,6 @@ __all__ = [
     "local_block_map",
     "block_update",
     "block_indices",
-    "gather_block",
-    "scatter_block",
     "apply_ops_local",
     "trace",
     "expectation",

@@ -6,7 +6,8 @@ sum_a L_a h_{s,s'} L_a^dagger.  Subroutine 1 (insertBits) rebuilds the global
 indices of a block from its subspace label.  This module implements that
 mathematics twice: once over a whole dense matrix by tensor contraction (used
 where the Kronecker form is too slow, n up to ~14) and once for single blocks
-(used to check sampled blocks of operators too large to hold densely).
+(used to check sampled blocks of operators too large to hold densely; the
+tests gather a block's rows and columns with :func:`block_indices`).
 """
 
 from __future__ import annotations
@@ -43,20 +44,6 @@ def block_indices(s: int, targets: Sequence[int]) -> np.ndarray:
             g |= ((u >> l) & 1) << t
         out[u] = g
     return out
-
-
-def gather_block(H: np.ndarray, s: int, s2: int, targets: Sequence[int]) -> np.ndarray:
-    """The block h_{s,s'} of Eq. (2) taken from a dense matrix."""
-    r = block_indices(s, targets)
-    c = block_indices(s2, targets)
-    return np.asarray(H)[np.ix_(r, c)].copy()
-
-
-def scatter_block(H: np.ndarray, s: int, s2: int, targets: Sequence[int], blk: np.ndarray) -> None:
-    """Write a block back into a dense matrix, in place."""
-    r = block_indices(s, targets)
-    c = block_indices(s2, targets)
-    H[np.ix_(r, c)] = blk
 
 
 def block_update(blk: np.ndarray, kraus: np.ndarray, adjoint: bool = False) -> np.ndarray:

@@ -275,3 +275,185 @@ def local_vs_dense_error(local_map, dense_map, n, rng) -> float:
         kraus = synth.random_kraus_set(len(t), 2, rng)
         worst = max(worst, rel(local_map(H, kraus, t), dense_map(H, kraus, t)))
     return worst
+
+
+# ---------------------------------------------------------------- blocks --
+
+def _digits_index(s, u, targets, n):
+    """Index built digit by digit (little-endian): the digit at targets[l] is
+    bit l of u, the remaining positions, in increasing order, take the bits of
+    s in order.  Written without bit insertion, as a check of it."""
+    k = len(targets)
+    s_bits = [(s >> b) & 1 for b in range(n - k)]
+    digits = []
+    for q in range(n):
+        if q in targets:
+            digits.append((u >> list(targets).index(q)) & 1)
+        else:
+            digits.append(s_bits.pop(0))
+    return sum(d << q for q, d in enumerate(digits))
+
+
+def block_indices_error(block_indices, n, target_sets) -> int:
+    """Eq. (2) and Subroutine 1: the 2^(n-k) invariant subspaces of a k-local
+    op partition the index range, and member u of subspace s has its target
+    bits spelling u (local bit l on targets[l], in the caller's order) and its
+    other bits spelling s.  Returns the number of violations (0 = pinned)."""
+    bad = 0
+    N = 1 << n
+    for targets in target_sets:
+        k = len(targets)
+        seen = np.zeros(N, dtype=np.int64)
+        for s in range(1 << (n - k)):
+            got = [int(v) for v in block_indices(s, targets)]
+            want = [_digits_index(s, u, targets, n) for u in range(1 << k)]
+            bad += sum(1 for a, b in zip(got, want) if a != b) + abs(len(got) - len(want))
+            for g in got:
+                if 0 <= g < N:
+                    seen[g] += 1
+                else:
+                    bad += 1
+        bad += int(np.count_nonzero(seen != 1))
+    return bad
+
+
+def block_form_consistency_error(block_indices, block_update, local_map, n, rng) -> float:
+    """Eq. (2): gathering block h_{s,s'} (rows of subspace s, columns of s')
+    after the whole-matrix map equals mapping the gathered block, for every
+    pair (s, s'), both pictures, and unsorted target orders."""
+    H = synth.random_hermitian_dense(n, rng)
+    worst = 0.0
+    for targets in ([2], [3, 1], [0, 4], [4, 2, 0] if n >= 5 else [2, 0, 1]):
+        k = len(targets)
+        kraus = synth.random_kraus_set(k, 2, rng) if k < 3 else synth.haar_unitary(8, rng)[None]
+        for adjoint in (False, True):
+            full = local_map(H, kraus, targets, adjoint=adjoint)
+            idx = [block_indices(s, targets) for s in range(1 << (n - k))]
+            for r in idx:
+                for c in idx:
+                    blk = block_update(H[np.ix_(r, c)], kraus, adjoint=adjoint)
+                    worst = max(worst, float(np.abs(full[np.ix_(r, c)] - blk).max()))
+    return worst
+
+
+# ----------------------------------------------------------- pauli sums --
+
+def _pauli_masks(codes_row):
+    """x marks X/Y positions, z marks Y/Z positions, ny counts the Y's."""
+    x = z = ny = 0
+    for q, c in enumerate(int(v) for v in codes_row):
+        if c in (1, 2):
+            x |= 1 << q
+        if c in (2, 3):
+            z |= 1 << q
+        ny += c == 2
+    return x, z, ny
+
+
+def _parity(v):
+    return bin(int(v)).count("1") & 1
+
+
+def pauli_sum_matrix_error(pauli_sum_matrix, n, rng, nterms=7) -> float:
+    """Section I's observables as Pauli sums, entry by entry: a string with
+    masks (x, z) and ny Y factors sends basis state j to
+    i^ny (-1)^popcount(j & z) |j xor x> (X flips a bit, Z signs it, Y = iXZ
+    does both), so O[j ^ x, j] gets c_t times that phase.  Random strings
+    over all four letters, including I on some qubits."""
+    N = 1 << n
+    codes = rng.integers(0, 4, size=(nterms, n))
+    codes[0, :] = 2  # an all-Y string: the phase i^n matters
+    coeffs = rng.standard_normal(nterms)
+    want = np.zeros((N, N), dtype=np.complex128)
+    for row, c in zip(codes, coeffs):
+        x, z, ny = _pauli_masks(row)
+        for j in range(N):
+            want[j ^ x, j] += c * (1j ** ny) * (-1.0 if _parity(j & z) else 1.0)
+    got = np.asarray(pauli_sum_matrix(codes, coeffs))
+    return float(np.abs(got - want).max())
+
+
+def pauli_sum_expectation_error(pauli_sum_expectation, n, rng, nterms=9) -> float:
+    """tr(rho O) for a Pauli sum from the masks alone: for each string,
+    sum_j (-i)^ny (-1)^popcount(j & z) rho[j ^ x, j], weighted by c_t and
+    summed (Section I).  Checked on a random density matrix."""
+    N = 1 << n
+    rho = random_density(n, rng)
+    codes = rng.integers(0, 4, size=(nterms, n))
+    codes[0, :] = 2
+    codes[1, :] = 0
+    codes[1, 0] = 2  # a single Y: the sign of (-i)^ny matters
+    coeffs = rng.standard_normal(nterms)
+    want = 0.0
+    for row, c in zip(codes, coeffs):
+        x, z, ny = _pauli_masks(row)
+        tot = 0.0 + 0.0j
+        for j in range(N):
+            tot += ((-1j) ** ny) * (-1.0 if _parity(j & z) else 1.0) * rho[j ^ x, j]
+        want += c * tot.real
+    return abs(float(pauli_sum_expectation(rho, codes, coeffs)) - want)
+
+
+# ------------------------------------------------------------- op order --
+
+def op_order_error(apply_ops, n=3, q=1, gamma=0.3) -> float:
+    """Section II-A: a circuit applies its maps one after the other.  X then
+    amplitude damping on qubit q takes |0><0| to gamma|0><0| + (1-gamma)|e><e|
+    (e = 2^q: X moves the population to bit q = 1, damping returns a fraction
+    gamma); the other order leaves |e><e|.  In the Heisenberg picture with the
+    ops given as [damping, X], the projector P1 on bit q = 1 goes to
+    (1-gamma) P0 (damping's adjoint keeps P1 scaled by 1-gamma, X's swaps it to
+    P0); the other order gives P1 + gamma P0.  Returns the largest deviation
+    from these hand-derived results."""
+    from types import SimpleNamespace
+
+    N = 1 << n
+    e = 1 << q
+    X = synth.named_gate("X")[None]
+    ad = synth.amplitude_damping_kraus(gamma)
+    opX = SimpleNamespace(targets=[q], mats=X)
+    opA = SimpleNamespace(targets=[q], mats=ad)
+    E0 = np.zeros((N, N), dtype=np.complex128)
+    E0[0, 0] = 1.0
+    want = np.zeros_like(E0)
+    want[0, 0] = gamma
+    want[e, e] = 1.0 - gamma
+    err = float(np.abs(apply_ops(E0, [opX, opA]) - want).max())
+    idx = np.arange(N)
+    P1 = np.diag(((idx >> q) & 1).astype(np.complex128))
+    P0 = np.eye(N, dtype=np.complex128) - P1
+    err = max(err, float(np.abs(apply_ops(P1, [opA, opX], adjoint=True) - (1.0 - gamma) * P0).max()))
+    return err
+
+
+# ------------------------------------------------------------- readouts --
+
+def trace_error(trace, n, rng) -> float:
+    """The trace is invariant under unitary similarity: tr(U diag(l) U^dagger)
+    = sum l for a Haar U; and tr I = N."""
+    N = 1 << n
+    lam = rng.standard_normal(N)
+    U = synth.haar_unitary(N, rng)
+    A = (U * lam) @ U.conj().T
+    err = abs(float(trace(A)) - float(lam.sum()))
+    err = max(err, abs(float(trace(np.eye(N, dtype=np.complex128))) - N))
+    return err
+
+
+def density_from_factor_error(density_from_factor, n, rng) -> float:
+    """rho = G G^dagger / tr: for a single column v the result is the
+    projector on v (rho v = v, rho^2 = rho); for r orthonormal columns scaled
+    by any c it is the projector on their span divided by r (eigenvalues 1/r,
+    r times, and 0)."""
+    N = 1 << n
+    v = rng.standard_normal((N, 1)) + 1j * rng.standard_normal((N, 1))
+    P = np.asarray(density_from_factor(v))
+    err = float(np.abs(P @ v - v).max() / np.abs(v).max())
+    err = max(err, float(np.abs(P @ P - P).max()))
+    r = 3
+    Q = synth.haar_unitary(N, rng)[:, :r] * (2.0 - 0.5j)
+    R = np.asarray(density_from_factor(Q))
+    ev = np.sort(np.linalg.eigvalsh((R + R.conj().T) / 2))
+    want = np.concatenate([np.zeros(N - r), np.full(r, 1.0 / r)])
+    err = max(err, float(np.abs(ev - want).max()), float(np.abs(R - R.conj().T).max()))
+    return err

@@ -273,3 +273,42 @@ def test_generators_are_deterministic():
     for kr in (synth.depolarising_kraus(0.1), synth.amplitude_damping_kraus(0.3),
                synth.dephasing_kraus(0.2), synth.random_kraus_set(2, 5, rng(81))):
         assert np.allclose(sum(L.conj().T @ L for L in kr), np.eye(kr.shape[1]), atol=1e-14)
+
+
+def test_block_indices_partition_and_digits():
+    """Subroutine 1 as used by Eq. (2): block_indices against a digit-string
+    construction, for sorted, unsorted, adjacent and distant target tuples;
+    the subspaces partition the index range."""
+    sets = [[0], [4], [1, 3], [3, 1], [4, 0], [0, 4], [2, 5], [5, 2, 0], [1, 4, 3]]
+    assert C.block_indices_error(oracle.block_indices, 6, sets) == 0
+
+
+def test_block_form_matches_whole_matrix_map():
+    """Every block h_{s,s'} of the mapped matrix equals Eq. (2) applied to the
+    gathered block (n = 5, every pair of subspaces, both pictures)."""
+    err = C.block_form_consistency_error(oracle.block_indices, oracle.block_update,
+                                         oracle.local_block_map, 5, rng(90))
+    assert err < 1e-14
+
+
+def test_pauli_sum_matrix_entrywise_closed_form():
+    for n in (1, 3, 5):
+        assert C.pauli_sum_matrix_error(oracle.pauli_sum_matrix, n, rng(91 + n)) < 1e-15
+
+
+def test_pauli_sum_expectation_closed_form():
+    for n in (1, 3, 5):
+        assert C.pauli_sum_expectation_error(oracle.pauli_sum_expectation, n, rng(95 + n)) < 1e-14
+
+
+def test_circuit_order_dense_and_local():
+    """Both circuit runners apply ops in the order given (hand-derived
+    results for X and amplitude damping, which do not commute)."""
+    assert C.op_order_error(oracle.apply_ops) < 1e-15
+    assert C.op_order_error(oracle.apply_ops_local) < 1e-15
+    assert C.op_order_error(oracle.apply_ops, n=4, q=3, gamma=0.05) < 1e-15
+
+
+def test_trace_and_density_from_factor():
+    assert C.trace_error(oracle.trace, 4, rng(99)) < 1e-12
+    assert C.density_from_factor_error(oracle.density_from_factor, 4, rng(100)) < 1e-13
