@@ -115,13 +115,25 @@ ht_status ht_herm_synchronize(ht_herm* h);
 
 /* ---------------------------------------------------------- init and IO -- */
 
+/* The init calls below fill the tiled format of Section III-B (lower tile
+ * triangle, full diagonal tiles) with an operand for the conjugation passes.
+ * The paper assumes an operator already in that format; these calls are the
+ * library's own way to build one on the device and name the operands the
+ * paper works with.  Each is enqueued on the handle's stream; argument
+ * errors return HT_EINVAL (NULL handle or pointer, out-of-range sizes) with
+ * the storage untouched. */
+
 /* H = 0. */
 ht_status ht_herm_init_zero(ht_herm* h);
 
-/* H = scale * I (scale = 1/N gives the maximally mixed state). */
+/* H = scale * I.  scale = 1/N gives the maximally mixed state, the fixed
+ * point of the depolarising channel of Section IV-A; scale = 1 gives the
+ * identity observable, which the Heisenberg map of a trace-preserving
+ * channel keeps (Section II-A, duality). */
 ht_status ht_herm_init_identity(ht_herm* h, double scale);
 
-/* H = the hermitian matrix whose lower triangle (i >= j) is that of the dense
+/* Section III-B: pack a dense operator into the tiled format.
+ * H = the hermitian matrix whose lower triangle (i >= j) is that of the dense
  * complex N x N row-major matrix A with leading dimension ld >= N (complex
  * entries).  Entries above the diagonal of A are not read: the stored upper
  * halves of diagonal tiles are set to the conjugates of the lower ones.
@@ -129,14 +141,21 @@ ht_status ht_herm_init_identity(ht_herm* h, double scale);
  * needs a temporary N x N device buffer).  A is not retained. */
 ht_status ht_herm_init_dense(ht_herm* h, const double* A, int64_t ld, int on_device);
 
-/* H = G G^dagger for a complex N x rank matrix G, row-major (rank entries per
+/* A density matrix of rank <= rank without a dense host copy (Section IV-A
+ * evolves randomly initialised operators; at n = 16 a dense one would be
+ * 64 GiB on the host).
+ * H = G G^dagger for a complex N x rank matrix G, row-major (rank entries per
  * row), 1 <= rank <= 4096.  on_device as above.  A normalised density matrix
  * follows with ht_trace and ht_scale. */
 ht_status ht_herm_init_lowrank(ht_herm* h, const double* G, int rank, int on_device);
 
-/* H = sum_t coeffs[t] P_t for Pauli strings P_t; codes is nterms x n (host,
+/* An observable for the Heisenberg picture (Section I: every prediction is
+ * tr(rho O), and the map may act on O instead of rho).  Each Pauli string is
+ * a permutation with signs (Section II-B: X swaps entries, Y swaps and
+ * negates, Z negates), so H is built entry by entry without any product.
+ * H = sum_t coeffs[t] P_t for Pauli strings P_t; codes is nterms x n (host,
  * row-major), codes[t*n + q] in {0=I, 1=X, 2=Y, 3=Z} acting on qubit q;
- * coeffs is host, real.  1 <= nterms <= 65536. */
+ * coeffs is host, real.  1 <= nterms <= 4096.  HT_EINVAL for a code > 3. */
 ht_status ht_herm_init_pauli_sum(ht_herm* h, int nterms, const uint8_t* codes,
                                  const double* coeffs);
 
@@ -210,8 +229,13 @@ ht_status ht_apply_channel(ht_herm* h, int k, const int* targets, int r, const d
 
 /* ----------------------------------------------------------- reductions -- */
 
-/* tr H = sum_i Re h_ii, accumulated in FP64 in a fixed order (deterministic).
- * out: host.  Synchronises. */
+/* The trace, tr(H I): the prediction of Section I for the identity
+ * observable, and what a trace-preserving map keeps (Section II-A: the maps
+ * are trace non-increasing; Section IV-A: the benchmarked channels preserve
+ * it).  The N diagonal entries live in the diagonal tiles (Section III-B).
+ * tr H = sum_i Re h_ii, accumulated in FP64 in a fixed order (deterministic,
+ * also for complex64 storage).  out: host.  Synchronises.  HT_EINVAL for a
+ * NULL handle or out. */
 ht_status ht_trace(const ht_herm* h, double* out);
 
 /* tr(A B) = Re sum_ij a_ij conj(b_ij) over the represented matrices, from the
@@ -220,13 +244,20 @@ ht_status ht_trace(const ht_herm* h, double* out);
  * same n, tile edge and dtype.  FP64, deterministic.  Synchronises. */
 ht_status ht_expectation(const ht_herm* a, const ht_herm* b, double* out);
 
-/* tr(H O) for O = sum_t coeffs[t] P_t (codes/coeffs as in
- * ht_herm_init_pauli_sum), read directly from the N entries each string
- * touches.  FP64, deterministic.  Synchronises. */
+/* Section I's prediction tr(H O) for a Pauli-sum observable
+ * O = sum_t coeffs[t] P_t (codes/coeffs as in ht_herm_init_pauli_sum,
+ * 1 <= nterms <= 4096).  A string with flip mask x and sign mask z touches
+ * N entries, tr(H P) = (-i)^ny sum_j (-1)^popcount(j & z) H[j ^ x, j]
+ * (the permutation-with-signs form of Section II-B), so no dense O is built.
+ * FP64, deterministic.  out: host.  Synchronises.  HT_EINVAL for a NULL
+ * argument, nterms out of range or a code > 3. */
 ht_status ht_expectation_pauli_sum(const ht_herm* h, int nterms, const uint8_t* codes,
                                    const double* coeffs, double* out);
 
-/* H = alpha * H (for example alpha = 1 / tr H to normalise). */
+/* H = alpha * H, in FP64 before the store.  Not an operation of the paper
+ * (its benchmark operator is not normalised, Section IV-A): the library's
+ * normalisation step, e.g. alpha = 1 / tr H for rho = G G^dagger / tr.
+ * Enqueued asynchronously.  HT_EINVAL for a NULL handle. */
 ht_status ht_scale(ht_herm* h, double alpha);
 
 /* ------------------------------------------------------------- batches -- */

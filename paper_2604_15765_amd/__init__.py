@@ -141,6 +141,60 @@ def _c128(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
 
 
+# Shape checks.  The C side receives bare pointers and reads as many entries
+# as the sizes imply, so every array is checked here before its address is
+# passed on; a mismatch raises ValueError and nothing is called.
+
+def _targets(targets) -> np.ndarray:
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    if t.ndim != 1 or not 1 <= t.shape[0] <= 3:
+        raise ValueError(f"targets must be a sequence of 1 to 3 qubits, got shape {t.shape}")
+    return t
+
+
+def _unitary(U, k: int) -> np.ndarray:
+    U = _c128(U)
+    d = 1 << k
+    if U.shape != (d, d):
+        raise ValueError(f"a {k}-qubit matrix must be {d} x {d}, got shape {U.shape}")
+    return U
+
+
+def _kraus(kraus, k: int) -> np.ndarray:
+    K = _c128(kraus)
+    if K.ndim == 2:
+        K = K[None]
+    d = 1 << k
+    if K.ndim != 3 or K.shape[1:] != (d, d) or K.shape[0] < 1:
+        raise ValueError(f"{k}-qubit Kraus operators must have shape (r, {d}, {d}), got {K.shape}")
+    return K
+
+
+def _pauli(codes, coeffs, n: int):
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if codes.ndim != 2 or codes.shape[1] != n or codes.shape[0] < 1:
+        raise ValueError(f"Pauli codes must have shape (nterms, {n}), got {codes.shape}")
+    if coeffs.shape != (codes.shape[0],):
+        raise ValueError(f"Pauli coefficients must have shape ({codes.shape[0]},), got {coeffs.shape}")
+    return codes, coeffs
+
+
+def _factor(G, n: int):
+    """(array or tensor, on_device) for a factor G of shape (2^n, rank)."""
+    N = 1 << n
+    if isinstance(G, torch.Tensor) and G.is_cuda:
+        if G.dtype != torch.complex128:
+            raise ValueError(f"a device factor must be complex128, got {G.dtype}")
+        if G.dim() != 2 or G.shape[0] != N or G.shape[1] < 1:
+            raise ValueError(f"the factor must have shape ({N}, rank), got {tuple(G.shape)}")
+        return G.contiguous(), True
+    G = _c128(G)
+    if G.ndim != 2 or G.shape[0] != N or G.shape[1] < 1:
+        raise ValueError(f"the factor must have shape ({N}, rank), got {G.shape}")
+    return G, False
+
+
 def storage_bytes(n: int, tile_log2: int, dtype: str = "c128") -> int:
     return int(lib.ht_storage_bytes(n, tile_log2, _DTYPES[dtype]))
 
@@ -211,7 +265,10 @@ class Herm:
             self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             if self.stream != torch.cuda.current_stream(self.device):
-                self.buffer.record_stream(self.stream)  # freed only after the stream's work
+                # the buffer was allocated on the current stream: order the
+                # handle's stream after it, and free it only after its work
+                self.stream.wait_stream(torch.cuda.current_stream(self.device))
+                self.buffer.record_stream(self.stream)
             h = ctypes.c_void_p()
             _check(lib.ht_herm_create(self.n, tile_log2, _DTYPES[dtype], ctypes.c_void_p(self.buffer.data_ptr()),
                                       nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
@@ -260,31 +317,43 @@ class Herm:
         _check(lib.ht_herm_init_identity(self._h, float(scale)))
         return self
 
+    def _use_on_stream(self, t: torch.Tensor) -> None:
+        """A device input read by work enqueued on the handle's stream: order
+        that stream after the tensor's producer and keep the memory alive until
+        the work has run."""
+        cur = torch.cuda.current_stream(self.device)
+        if self.stream != cur:
+            self.stream.wait_stream(cur)
+        t.record_stream(self.stream)
+
     def init_dense(self, A) -> "Herm":
+        N = 1 << self.n
         if isinstance(A, torch.Tensor) and A.is_cuda:
-            A = A.contiguous()
             if A.dtype != torch.complex128:
-                raise TypeError("device matrices must be complex128")
+                raise ValueError(f"a device matrix must be complex128, got {A.dtype}")
+            if A.dim() != 2 or A.shape[0] != N or A.shape[1] < N:
+                raise ValueError(f"the matrix must have shape ({N}, >= {N}), got {tuple(A.shape)}")
+            A = A.contiguous()
+            self._use_on_stream(A)
             _check(lib.ht_herm_init_dense(self._h, ctypes.c_void_p(A.data_ptr()), A.shape[1], 1))
-            self._keep = A
             return self
         A = _c128(A)
+        if A.ndim != 2 or A.shape[0] != N or A.shape[1] < N:
+            raise ValueError(f"the matrix must have shape ({N}, >= {N}), got {A.shape}")
         _check(lib.ht_herm_init_dense(self._h, _ptr(A), A.shape[1], 0))
         return self
 
     def init_lowrank(self, G) -> "Herm":
-        if isinstance(G, torch.Tensor) and G.is_cuda:
-            G = G.contiguous()
+        G, on_device = _factor(G, self.n)
+        if on_device:
+            self._use_on_stream(G)
             _check(lib.ht_herm_init_lowrank(self._h, ctypes.c_void_p(G.data_ptr()), G.shape[1], 1))
-            self._keep = G
             return self
-        G = _c128(G)
         _check(lib.ht_herm_init_lowrank(self._h, _ptr(G), G.shape[1], 0))
         return self
 
     def init_pauli_sum(self, codes, coeffs) -> "Herm":
-        codes = np.ascontiguousarray(codes, dtype=np.uint8)
-        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        codes, coeffs = _pauli(codes, coeffs, self.n)
         _check(lib.ht_herm_init_pauli_sum(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs)))
         return self
 
@@ -321,16 +390,14 @@ class Herm:
 
     # hot path ----------------------------------------------------------
     def apply_unitary(self, targets: Sequence[int], U, picture: int = SCHRODINGER) -> None:
-        U = _c128(U)
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_apply_unitary(self._h, len(targets), _ptr(t), _ptr(U), picture))
+        t = _targets(targets)
+        U = _unitary(U, t.shape[0])
+        _check(lib.ht_apply_unitary(self._h, t.shape[0], _ptr(t), _ptr(U), picture))
 
     def apply_channel(self, targets: Sequence[int], kraus, picture: int = SCHRODINGER) -> None:
-        K = _c128(kraus)
-        if K.ndim == 2:
-            K = K[None]
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_apply_channel(self._h, len(targets), _ptr(t), K.shape[0], _ptr(K), picture))
+        t = _targets(targets)
+        K = _kraus(kraus, t.shape[0])
+        _check(lib.ht_apply_channel(self._h, t.shape[0], _ptr(t), K.shape[0], _ptr(K), picture))
 
     def apply_op(self, op, picture: int = SCHRODINGER) -> None:
         """Apply an op with ``kind``, ``targets`` and ``mats`` (see ``synth.Op``)."""
@@ -351,8 +418,7 @@ class Herm:
         return out.value
 
     def expectation_pauli_sum(self, codes, coeffs) -> float:
-        codes = np.ascontiguousarray(codes, dtype=np.uint8)
-        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        codes, coeffs = _pauli(codes, coeffs, self.n)
         out = ctypes.c_double()
         _check(lib.ht_expectation_pauli_sum(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs),
                                             ctypes.byref(out)))
@@ -420,17 +486,15 @@ class Batch:
         _check(lib.ht_batch_set_param(self._b, name.encode(), int(value)))
 
     def add_unitary(self, h: Herm, targets, U, picture: int = SCHRODINGER) -> None:
-        U = _c128(U)
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_batch_add_unitary(self._b, h.handle, len(targets), _ptr(t), _ptr(U), picture))
+        t = _targets(targets)
+        U = _unitary(U, t.shape[0])
+        _check(lib.ht_batch_add_unitary(self._b, h.handle, t.shape[0], _ptr(t), _ptr(U), picture))
         self._keep[id(h)] = h
 
     def add_channel(self, h: Herm, targets, kraus, picture: int = SCHRODINGER) -> None:
-        K = _c128(kraus)
-        if K.ndim == 2:
-            K = K[None]
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_batch_add_channel(self._b, h.handle, len(targets), _ptr(t), K.shape[0], _ptr(K),
+        t = _targets(targets)
+        K = _kraus(kraus, t.shape[0])
+        _check(lib.ht_batch_add_channel(self._b, h.handle, t.shape[0], _ptr(t), K.shape[0], _ptr(K),
                                         picture))
         self._keep[id(h)] = h
 
@@ -492,16 +556,14 @@ class Circuit:
             self.add_op(op)
 
     def add_unitary(self, targets, U) -> None:
-        U = _c128(U)
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_circuit_add_unitary(self._c, len(targets), _ptr(t), _ptr(U)))
+        t = _targets(targets)
+        U = _unitary(U, t.shape[0])
+        _check(lib.ht_circuit_add_unitary(self._c, t.shape[0], _ptr(t), _ptr(U)))
 
     def add_channel(self, targets, kraus) -> None:
-        K = _c128(kraus)
-        if K.ndim == 2:
-            K = K[None]
-        t = np.ascontiguousarray(targets, dtype=np.int32)
-        _check(lib.ht_circuit_add_channel(self._c, len(targets), _ptr(t), K.shape[0], _ptr(K)))
+        t = _targets(targets)
+        K = _kraus(kraus, t.shape[0])
+        _check(lib.ht_circuit_add_channel(self._c, t.shape[0], _ptr(t), K.shape[0], _ptr(K)))
 
     def add_op(self, op) -> None:
         if op.kind == "unitary":
@@ -621,20 +683,26 @@ class Server:
     def submit(self, n: int, G, ops, pauli=None, dtype: str = "c128", picture: int = SCHRODINGER) -> int:
         """Queue a request: state G G^dagger / tr, ops (objects with targets and
         mats), readout tr(rho O) for pauli = (codes, coeffs) or the trace."""
-        G = _c128(G)
-        k = np.array([len(op.targets) for op in ops], dtype=np.int32)
+        if isinstance(G, torch.Tensor):
+            G = G.detach().cpu().numpy()
+        G, _ = _factor(G, int(n))
         tg = np.zeros(2 * len(ops), dtype=np.int32)
+        blocks = []
         for i, op in enumerate(ops):
-            tg[2 * i:2 * i + len(op.targets)] = op.targets
-        r = np.array([op.mats.shape[0] for op in ops], dtype=np.int32)
-        mats = (np.ascontiguousarray(np.concatenate([np.asarray(op.mats, np.complex128).reshape(-1) for op in ops]))
+            t = _targets(op.targets)
+            if t.shape[0] > 2:
+                raise ValueError(f"op {i}: served requests take 1- and 2-qubit ops, got {t.shape[0]} targets")
+            tg[2 * i:2 * i + t.shape[0]] = t
+            blocks.append(_kraus(op.mats, t.shape[0]))
+        k = np.array([len(op.targets) for op in ops], dtype=np.int32)
+        r = np.array([b.shape[0] for b in blocks], dtype=np.int32)
+        mats = (np.ascontiguousarray(np.concatenate([b.reshape(-1) for b in blocks]))
                 if ops else np.zeros(1, np.complex128))
         req = _Request(n=n, dtype=_DTYPES[dtype], rank=G.shape[1], G=G.ctypes.data, nops=len(ops),
                        op_k=k.ctypes.data, op_targets=tg.ctypes.data, op_r=r.ctypes.data,
                        op_mats=mats.ctypes.data, picture=picture, nterms=0, codes=None, coeffs=None)
         if pauli is not None:
-            codes = np.ascontiguousarray(pauli[0], dtype=np.uint8)
-            coeffs = np.ascontiguousarray(pauli[1], dtype=np.float64)
+            codes, coeffs = _pauli(pauli[0], pauli[1], int(n))
             req.nterms, req.codes, req.coeffs = codes.shape[0], codes.ctypes.data, coeffs.ctypes.data
         rid = ctypes.c_int64()
         _check(lib.ht_server_submit(self._s, ctypes.byref(req), ctypes.byref(rid)))

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 import oracle
+from tests import sampling
 import synth
 from oracle import layout
 from tests.native_masks import changing_entries, expected_writes
@@ -215,15 +216,8 @@ def test_native_full_size_sampled_blocks(ht, n):
         synth.random_ops.channel_op([n - 1, 0, 6], synth.random_kraus_set(3, 2, rng)),  # Kraus form
     ]
     for i, op in enumerate(ops):
-        k = len(op.targets)
         nblocks = 1500
-        s = rng.integers(0, 1 << (n - k), size=nblocks)
-        s2 = rng.integers(0, 1 << (n - k), size=nblocks)
-        rows = np.stack([oracle.block_indices(int(x), op.targets) for x in s])
-        cols = np.stack([oracle.block_indices(int(x), op.targets) for x in s2])
-        d = 1 << k
-        R = np.repeat(rows[:, :, None], d, axis=2).reshape(-1)
-        C = np.repeat(cols[:, None, :], d, axis=1).reshape(-1)
+        R, C, d = sampling.block_entries(n, op.targets, h.tile_log2, nblocks, rng)
         before = h.get_entries(R, C).reshape(nblocks, d, d)
         pic = i % 2
         h.apply_op(op, pic)

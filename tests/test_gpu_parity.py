@@ -15,6 +15,7 @@ import torch
 import oracle
 import synth
 from oracle import layout
+from tests import sampling
 
 pytestmark = pytest.mark.gpu
 
@@ -222,6 +223,9 @@ def test_plain_n8_circuit(ht):
         ref = oracle.apply_ops(rho0, ops)
         assert rel(h.to_dense(), ref) <= TOL
         assert abs(h.trace() - oracle.trace(ref)) < 1e-13
+        # the stored upper halves of diagonal tiles (Section III-B keeps all
+        # M^2 entries; Subroutine 4 writes them) match the conjugated lower ones
+        assert layout.diagonal_tile_asymmetry(h.raw_entries(), 8, h.tile_log2) <= 1e-14
 
 
 def test_sweep_circuit_and_heisenberg_duality(ht):
@@ -238,11 +242,13 @@ def test_sweep_circuit_and_heisenberg_duality(ht):
         rho.apply_op(op)
     ref = oracle.apply_ops_local(rho0, ops)
     assert rel(rho.to_dense(), ref) <= TOL
+    assert layout.diagonal_tile_asymmetry(rho.raw_entries(), n, m) <= 1e-14
     O = ht.Herm(n, m).init_pauli_sum(codes, coeffs)
     for op in reversed(ops):
         O.apply_op(op, ht.HEISENBERG)
     O_ref = oracle.apply_ops_local(oracle.pauli_sum_matrix(codes, coeffs), list(reversed(ops)), adjoint=True)
     assert rel(O.to_dense(), O_ref) <= TOL
+    assert layout.diagonal_tile_asymmetry(O.raw_entries(), n, m) <= 1e-14
     rho_init = ht.Herm(n, m)
     rho_init.init_lowrank(G)
     rho_init.scale(1.0 / rho_init.trace())
@@ -292,6 +298,84 @@ def test_invalid_arguments_leave_state_untouched(ht):
     assert np.array_equal(h.to_dense(), lower_hermitian(H))
 
 
+def test_error_paths_through_the_c_abi(ht):
+    """Every argument error of create, init, apply and the reductions returns
+    its status code through the C ABI and leaves the storage bitwise as it
+    was (HT_EINVAL = 1, HT_ENOMEM = 2)."""
+    import ctypes
+
+    lib = ht.lib
+    EINVAL, ENOMEM = 1, 2
+    out = ctypes.c_void_p()
+    for n, m in ((5, 0), (5, 9), (0, 5), (19, 5), (-1, 3)):
+        assert lib.ht_herm_create(n, m, 0, None, 0, None, ctypes.byref(out)) == EINVAL, (n, m)
+        assert out.value is None
+    assert lib.ht_herm_create(5, 2, 2, None, 0, None, ctypes.byref(out)) == EINVAL   # dtype
+    assert lib.ht_herm_create(5, 2, 0, None, 0, None, None) == EINVAL                # out NULL
+    need = ht.storage_bytes(5, 2)
+    raw = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    base = (raw.data_ptr() + 255) // 256 * 256
+    assert lib.ht_herm_create(5, 2, 0, ctypes.c_void_p(base + 16), need, None, ctypes.byref(out)) == EINVAL
+    assert lib.ht_herm_create(5, 2, 0, ctypes.c_void_p(base), need - 1, None, ctypes.byref(out)) == ENOMEM
+    assert out.value is None
+    assert lib.ht_herm_create(5, 2, 0, ctypes.c_void_p(base), need, None, ctypes.byref(out)) == 0
+    assert lib.ht_herm_destroy(out) == 0
+
+    rng = synth.make_rng(501)
+    n, m = 5, 2
+    H = synth.random_hermitian_dense(n, rng)
+    a = make(ht, n, m, H)
+    b64 = make(ht, n, m, H, dtype="c64")
+    b3 = make(ht, n, 3, H)
+    before = [x.read_raw() for x in (a, b64, b3)]
+    res = ctypes.c_double(12345.0)
+    for other in (b64, b3, make(ht, 6, m)):
+        assert lib.ht_expectation(a.handle, other.handle, ctypes.byref(res)) == EINVAL
+    assert lib.ht_expectation(a.handle, a.handle, None) == EINVAL
+    assert lib.ht_expectation(None, a.handle, ctypes.byref(res)) == EINVAL
+    assert lib.ht_trace(a.handle, None) == EINVAL
+    assert lib.ht_trace(None, ctypes.byref(res)) == EINVAL
+    assert res.value == 12345.0
+    codes = np.zeros((2, n), np.uint8)
+    coeffs = np.ones(2)
+    P = lambda x: ctypes.c_void_p(x.ctypes.data)
+    for nt in (0, 4097):
+        assert lib.ht_expectation_pauli_sum(a.handle, nt, P(codes), P(coeffs), ctypes.byref(res)) == EINVAL
+    assert lib.ht_expectation_pauli_sum(a.handle, 2, None, P(coeffs), ctypes.byref(res)) == EINVAL
+    assert lib.ht_expectation_pauli_sum(a.handle, 2, P(codes), None, ctypes.byref(res)) == EINVAL
+    assert lib.ht_expectation_pauli_sum(a.handle, 2, P(codes), P(coeffs), None) == EINVAL
+    bad_codes = codes.copy()
+    bad_codes[1, 3] = 4
+    assert lib.ht_expectation_pauli_sum(a.handle, 2, P(bad_codes), P(coeffs), ctypes.byref(res)) == EINVAL
+    assert lib.ht_herm_init_pauli_sum(a.handle, 2, P(bad_codes), P(coeffs)) == EINVAL
+    assert lib.ht_herm_init_pauli_sum(a.handle, 0, P(codes), P(coeffs)) == EINVAL
+    G = synth.ginibre_factor(n, 2, rng)
+    for rank in (0, 4097):
+        assert lib.ht_herm_init_lowrank(a.handle, P(G), rank, 0) == EINVAL
+    assert lib.ht_herm_init_lowrank(a.handle, None, 2, 0) == EINVAL
+    D = np.ascontiguousarray(H)
+    assert lib.ht_herm_init_dense(a.handle, P(D), (1 << n) - 1, 0) == EINVAL
+    assert lib.ht_herm_init_dense(a.handle, None, 1 << n, 0) == EINVAL
+    U = np.ascontiguousarray(synth.haar_unitary(4, rng))
+    t = np.array([0, 3, 4], np.int32)
+    for k in (0, 4):
+        assert lib.ht_apply_unitary(a.handle, k, P(t), P(U), 0) == EINVAL
+    assert lib.ht_apply_unitary(a.handle, 2, None, P(U), 0) == EINVAL
+    assert lib.ht_apply_unitary(a.handle, 2, P(t), None, 0) == EINVAL
+    assert lib.ht_apply_unitary(a.handle, 2, P(t), P(U), 2) == EINVAL                 # picture
+    assert lib.ht_apply_channel(a.handle, 2, P(t), 0, P(U), 0) == EINVAL               # r = 0
+    assert lib.ht_apply_channel(a.handle, 2, P(t), 17, P(U), 0) == EINVAL              # r > 4^k
+    assert lib.ht_apply_unitary(None, 2, P(t), P(U), 0) == EINVAL
+    assert lib.ht_scale(None, 2.0) == EINVAL
+    assert lib.ht_herm_init_zero(None) == EINVAL
+    assert lib.ht_herm_init_identity(None, 1.0) == EINVAL
+    assert lib.ht_last_error()  # a message was recorded
+    after = [x.read_raw() for x in (a, b64, b3)]
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.to_dense(), lower_hermitian(H))
+
+
 def test_borrowed_buffer_survives_destroy(ht):
     h = ht.Herm(6, 3)
     buf = h.buffer
@@ -305,20 +389,12 @@ def test_borrowed_buffer_survives_destroy(ht):
 # --------------------------------------------------------- full sizes
 
 
-def _sampled_blocks(n, targets, nblocks, rng):
-    k = len(targets)
-    s = rng.integers(0, 1 << (n - k), size=nblocks)
-    s2 = rng.integers(0, 1 << (n - k), size=nblocks)
-    rows = np.stack([oracle.block_indices(int(x), targets) for x in s])
-    cols = np.stack([oracle.block_indices(int(x), targets) for x in s2])
-    d = 1 << k
-    R = np.repeat(rows[:, :, None], d, axis=2).reshape(nblocks, -1)
-    C = np.repeat(cols[:, None, :], d, axis=1).reshape(nblocks, -1)
-    return R.reshape(-1), C.reshape(-1), d
-
-
 def _sampled_op_check(h, op, picture, n, rng, nblocks=1500):
-    R, C, d = _sampled_blocks(n, op.targets, nblocks, rng)
+    """Blocks drawn with at least 120 in diagonal tile groups and 120 in the
+    last tile row (tests/sampling.py), the rest uniform."""
+    R, C, d = sampling.block_entries(n, op.targets, h.tile_log2, nblocks, rng)
+    ndiag, nlast = sampling.strata_counts(n, op.targets, h.tile_log2, R, C, d)
+    assert ndiag >= 100 and nlast >= 100, (ndiag, nlast)
     before = h.get_entries(R, C).reshape(nblocks, d, d)
     h.apply_op(op, picture)
     after = h.get_entries(R, C).reshape(nblocks, d, d)
