@@ -254,6 +254,27 @@ ht_status ht_expectation(const ht_herm* a, const ht_herm* b, double* out);
 ht_status ht_expectation_pauli_sum(const ht_herm* h, int nterms, const uint8_t* codes,
                                    const double* coeffs, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as ht_expectation_pauli_sum, bit for bit (the same kernels, the
+ * same term order and summation order), with the term table, the partial
+ * sums and the result held in one fixed device array of
+ * HT_NOALLOC_SCRATCH_BYTES bytes per GPU instead of buffers the handle
+ * allocates.  The array is taken on a GPU's first call and held by that GPU
+ * until the process ends.  Makes no device allocation or free.
+ * 1 <= nterms <= HT_NOALLOC_MAX_TERMS; more terms return HT_EINVAL (use
+ * ht_expectation_pauli_sum).  Other arguments and errors as for
+ * ht_expectation_pauli_sum; out: host; synchronises the handle's stream.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (every slot a call reads is written by that call first): calls
+ * that overlap on one GPU (from several threads, or on several handles of
+ * one GPU with their streams running concurrently) race and must be
+ * serialised by the caller. */
+#define HT_NOALLOC_MAX_TERMS 256
+#define HT_NOALLOC_SCRATCH_BYTES 268544
+ht_status ht_expectation_pauli_sum_noalloc(const ht_herm* h, int nterms, const uint8_t* codes,
+                                           const double* coeffs, double* out);
+
 /* H = alpha * H, in FP64 before the store.  Not an operation of the paper
  * (its benchmark operator is not normalised, Section IV-A): the library's
  * normalisation step, e.g. alpha = 1 / tr H for rho = G G^dagger / tr.

@@ -80,6 +80,7 @@ def _load():
         "ht_trace": (c_int, [vp, P(c_double)]),
         "ht_expectation": (c_int, [vp, vp, P(c_double)]),
         "ht_expectation_pauli_sum": (c_int, [vp, c_int, vp, vp, P(c_double)]),
+        "ht_expectation_pauli_sum_noalloc": (c_int, [vp, c_int, vp, vp, P(c_double)]),
         "ht_scale": (c_int, [vp, c_double]),
         "ht_last_error": (ctypes.c_char_p, []),
         "ht_profile_enable": (c_int, [vp, c_int]),
@@ -422,6 +423,15 @@ class Herm:
         out = ctypes.c_double()
         _check(lib.ht_expectation_pauli_sum(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs),
                                             ctypes.byref(out)))
+        return out.value
+
+    def expectation_pauli_sum_noalloc(self, codes, coeffs) -> float:
+        """expectation_pauli_sum through the entry point that allocates no
+        device memory (at most 256 terms; calls on one GPU must not overlap)."""
+        codes, coeffs = _pauli(codes, coeffs, self.n)
+        out = ctypes.c_double()
+        _check(lib.ht_expectation_pauli_sum_noalloc(self._h, codes.shape[0], _ptr(codes), _ptr(coeffs),
+                                                    ctypes.byref(out)))
         return out.value
 
     def scale(self, alpha: float) -> None:
