@@ -619,6 +619,52 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().native = (int)value;
     return HT_OK;
   }
+  if (k == "stage") {
+    if (value < -1 || value > 1) return ht_fail(HT_EINVAL, "stage must be -1, 0 or 1");
+    ht::tuning().stage = (int)value;
+    return HT_OK;
+  }
+  if (k == "stage_wg_per_cu") {
+    if (value < 1 || value > 2) return ht_fail(HT_EINVAL, "stage_wg_per_cu must be 1 or 2");
+    ht::tuning().stage_wg_per_cu = (int)value;
+    return HT_OK;
+  }
+  if (k == "stage_pipe") {
+    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "stage_pipe must be 0 or 1");
+    ht::tuning().stage_pipe = (int)value;
+    return HT_OK;
+  }
+  if (k == "stage_threads") {
+    if (value != 256 && value != 512) return ht_fail(HT_EINVAL, "stage_threads must be 256 or 512");
+    ht::tuning().stage_threads = (int)value;
+    return HT_OK;
+  }
+  if (k == "sync_waves") {
+    if (value != -1 && value != 0 && value != 4 && value != 8 && value != 16)
+      return ht_fail(HT_EINVAL, "sync_waves must be -1, 0, 4, 8 or 16");
+    ht::tuning().sync_waves = (int)value;
+    return HT_OK;
+  }
+  if (k == "pipe_waves") {
+    if (value != 0 && value != 4 && value != 8) return ht_fail(HT_EINVAL, "pipe_waves must be 0, 4 or 8");
+    ht::tuning().pipe_waves = (int)value;
+    return HT_OK;
+  }
+  if (k == "sync_interleave") {
+    if (value < -1 || value > 1) return ht_fail(HT_EINVAL, "sync_interleave must be -1, 0 or 1");
+    ht::tuning().sync_interleave = (int)value;
+    return HT_OK;
+  }
+  if (k == "pipe_barrier") {
+    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "pipe_barrier must be 0 or 1");
+    ht::tuning().pipe_barrier = (int)value;
+    return HT_OK;
+  }
+  if (k == "sync_wg_per_cu") {
+    if (value < 1 || value > 8) return ht_fail(HT_EINVAL, "sync_wg_per_cu must be in [1, 8]");
+    ht::tuning().sync_wg_per_cu = (int)value;
+    return HT_OK;
+  }
   if (k == "conj_mem_mode") {
     if (value < -1 || value > 3) return ht_fail(HT_EINVAL, "conj_mem_mode must be in [-1, 3]");
     ht::tuning().mem_mode = (int)value;

@@ -57,6 +57,264 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------------------------- workgroup-wide steps
+
+// The pass with its steps taken by a whole workgroup at once: the waves of a
+// workgroup take consecutive (group, step) items -- whole groups of
+// neighbouring tiles when a workgroup has as many waves as a group has steps
+// -- load all their blocks, meet at a barrier, then compute and store.  Every
+// tile run that the workgroup covers in one step is then read completely
+// before any of it is written back (measured on MI355X: in-place streams run
+// faster in long read and write bursts than when each wave alternates on its
+// own).  Same lanes, same block arithmetic as conj_kernel: bitwise the same
+// results.
+template <typename T, int K, int C, int FORM, int MODE>
+__global__ void __launch_bounds__(1024)
+    conj_sync_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
+                     const double* __restrict__ coef) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wpb = blockDim.x >> 6;
+  const DirectMem<T, MODE, (K == 1 && C > 0)> mem{h};
+  using Mem = decltype(mem);
+  if constexpr (K == 2 && FORM == 1) cf.p = coef;
+  constexpr int JU = conj_unroll(K, (int)sizeof(T) * 2);
+  constexpr int D = 1 << K;
+  const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
+  const int sl = 31 - __builtin_clz(steps);
+  const uint64_t items = g.ngroups << sl;
+  const uint32_t nblk = 1u << (2 * g.F);
+  // the loop bound is the same for every wave of the workgroup (barrier)
+  for (uint64_t base = (uint64_t)blockIdx.x * wpb; base < items; base += (uint64_t)gridDim.x * wpb) {
+    const uint64_t it = base + wib;
+    const bool valid = it < items;
+    GroupCtx<C> gc;
+    group_ctx<K, C>(valid ? (it >> sl) : 0, g, gc);
+    const uint32_t j0 = (uint32_t)(it & (steps - 1)) * JU;
+    BlockPos bp[JU];
+    typename Mem::R x[JU][D * D];
+#pragma unroll
+    for (int j = 0; j < JU; ++j) {
+      const uint32_t b = (j0 + j) * 64u + lane;
+      bp[j] = block_pos<K, C>(g, gc, b, valid && j0 + j < g.jobs && b < nblk);
+      block_load<K, C>(mem, g, gc, bp[j], x[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < JU; ++j)
+      if (bp[j].active) block_update_store<K, C, FORM>(mem, g, gc, cf, bp[j], x[j]);
+  }
+}
+
+// The workgroup-wide steps with the next step's loads issued before the
+// current step is computed: every wave holds two steps of blocks in
+// registers, so the FP64 work of one step overlaps the loads of the next.
+// All waves of the workgroup have their current step loaded before any of
+// them stores it (a barrier after each wave's own wait).
+template <int JU, int K, int C, typename Mem>
+struct PipeSlot {
+  GroupCtx<C> gc;
+  BlockPos bp[JU];
+  typename Mem::R x[JU][(1 << K) * (1 << K)];
+};
+
+template <int JU, int K, int C, typename Mem>
+__device__ inline void pipe_load(const Mem& mem, const ConjGeom<K, C>& g, uint64_t it, uint64_t items, int sl,
+                                 uint32_t lane, PipeSlot<JU, K, C, Mem>& sl_) {
+  const bool valid = it < items;
+  group_ctx<K, C>(valid ? (it >> sl) : 0, g, sl_.gc);
+  const uint32_t steps_mask = (1u << sl) - 1u;
+  const uint32_t j0 = (uint32_t)(it & steps_mask) * JU;
+  const uint32_t nblk = 1u << (2 * g.F);
+#pragma unroll
+  for (int j = 0; j < JU; ++j) {
+    const uint32_t b = (j0 + j) * 64u + lane;
+    sl_.bp[j] = block_pos<K, C>(g, sl_.gc, b, valid && j0 + j < g.jobs && b < nblk);
+    block_load<K, C>(mem, g, sl_.gc, sl_.bp[j], sl_.x[j]);
+  }
+}
+
+// Wait for this lane's loads of a slot (an empty asm that reads every loaded
+// register makes the compiler wait for them), then meet the other waves.
+template <int JU, int K, int C, typename Mem, bool BAR>
+__device__ inline void pipe_arrive(PipeSlot<JU, K, C, Mem>& sl_) {
+#pragma unroll
+  for (int j = 0; j < JU; ++j)
+#pragma unroll
+    for (int e = 0; e < (1 << K) * (1 << K); ++e) {
+      if constexpr (Mem::kNarrow)
+        asm volatile("" ::"v"(sl_.x[j][e].v));
+      else
+        asm volatile("" ::"v"(sl_.x[j][e].re), "v"(sl_.x[j][e].im));
+    }
+  if constexpr (BAR) __builtin_amdgcn_s_barrier();
+}
+
+template <int JU, int K, int C, int FORM, typename Mem>
+__device__ inline void pipe_store(const Mem& mem, const ConjGeom<K, C>& g, const Coef<K, FORM>& cf,
+                                  PipeSlot<JU, K, C, Mem>& sl_) {
+#pragma unroll
+  for (int j = 0; j < JU; ++j)
+    if (sl_.bp[j].active) block_update_store<K, C, FORM>(mem, g, sl_.gc, cf, sl_.bp[j], sl_.x[j]);
+}
+
+template <typename T, int K, int C, int FORM, int MODE, int NTH, bool BAR>
+__global__ void __launch_bounds__(NTH)
+    conj_pipe_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
+                     const double* __restrict__ coef) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr uint32_t wpb = NTH / 64;
+  using Mem = DirectMem<T, MODE, (K == 1 && C > 0)>;
+  const Mem mem{h};
+  if constexpr (K == 2 && FORM == 1) cf.p = coef;
+  constexpr int JU = conj_unroll(K, (int)sizeof(T) * 2);
+  const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
+  const int sl = 31 - __builtin_clz(steps);
+  const uint64_t items = g.ngroups << sl;
+  const uint64_t stride = (uint64_t)gridDim.x * wpb;
+  uint64_t base = (uint64_t)blockIdx.x * wpb;
+  if (base >= items) return;  // the whole workgroup
+  PipeSlot<JU, K, C, Mem> a, b;
+  pipe_load<JU, K, C>(mem, g, base + wib, items, sl, lane, a);
+  // two steps per turn, so that the slots alternate without copies; every
+  // bound below is the same for all waves of the workgroup
+  // The prefetch is issued unconditionally (past the end it reads the first
+  // entry of group 0's tiles): a load behind a branch would make the
+  // compiler wait for every outstanding load, the prefetch included, before
+  // the current step is used.
+  for (;;) {
+    uint64_t nb = base + stride;
+    pipe_load<JU, K, C>(mem, g, nb + wib, items, sl, lane, b);
+    pipe_arrive<JU, K, C, Mem, BAR>(a);
+    pipe_store<JU, K, C, FORM>(mem, g, cf, a);
+    if (nb >= items) break;
+    base = nb;
+    nb = base + stride;
+    pipe_load<JU, K, C>(mem, g, nb + wib, items, sl, lane, a);
+    pipe_arrive<JU, K, C, Mem, BAR>(b);
+    pipe_store<JU, K, C, FORM>(mem, g, cf, b);
+    if (nb >= items) break;
+    base = nb;
+  }
+}
+
+// ------------------------------------------------------- LDS-staged intra pass
+
+// Intra-tile passes (Algorithm 2: every target inside the tile, every stored
+// tile handled alike, diagonal tiles in both halves) staged through LDS.
+// Tiles are contiguous in storage, so a workgroup step takes the next 64 KiB
+// of the buffer -- 4096 / M^2 whole tiles of 16-byte entries, twice as many
+// of 8-byte ones -- with 1 KiB nontemporal loads per wave instruction, puts
+// it in LDS, applies the operation to every block of those tiles out of LDS,
+// and writes the 64 KiB back the same way.  Global accesses are whole lines
+// whatever the target bits; the block arithmetic is that of conj_kernel
+// (block_apply), so results are bitwise the same.
+constexpr int kStageVecs = 16;                 // 16-byte vectors per thread and step
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
+// not for its global loads (a prefetch may stay in flight across it).
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <typename T, int K, int FORM, int kStageThreads, bool PIPE>
+__global__ void __launch_bounds__(kStageThreads)
+    stage_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, 0> g, Coef<K, FORM> cf,
+                 const double* __restrict__ coef, uint64_t total) {
+  using S2 = typename store2<T>::type;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr uint32_t EPV = 16 / sizeof(S2);                 // entries per vector
+  constexpr uint32_t CAPV = kStageVecs * kStageThreads;     // vectors per step
+  constexpr uint32_t CAP = CAPV * EPV;                      // entries per step
+  constexpr int D = 1 << K;
+  __shared__ u4 lds[CAPV];
+  if constexpr (K == 2 && FORM == 1) cf.p = coef;
+  const uint32_t t = threadIdx.x;
+  const int m = g.m;
+  const int F = g.F;
+  const uint32_t bpt_log = 2u * (uint32_t)F;                // blocks per tile = 4^F
+  const uint64_t nsteps = (total + CAP - 1) / CAP;
+  u4* __restrict__ hv = reinterpret_cast<u4*>(h);
+  S2* le = reinterpret_cast<S2*>(lds);
+  // vectors of step st that lie in the buffer (whole tiles; the last step may be short)
+  auto count_v = [&](uint64_t st) -> uint32_t {
+    const uint64_t left = total - st * CAP;
+    return (left < CAP ? (uint32_t)left : CAP) / EPV;
+  };
+  auto load_step = [&](uint64_t st, u4 (&v)[kStageVecs]) {
+    const u4* src = hv + st * CAPV;
+    const uint32_t cntv = count_v(st);
+    if (cntv == CAPV) {
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) v[j] = __builtin_nontemporal_load(src + j * kStageThreads + t);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) {
+        const uint32_t i = j * kStageThreads + t;
+        if (i < cntv) v[j] = __builtin_nontemporal_load(src + i);
+      }
+    }
+  };
+  u4 v[kStageVecs];
+  uint64_t st = blockIdx.x;
+  if (PIPE && st < nsteps) load_step(st, v);
+  for (; st < nsteps; st += gridDim.x) {
+    const uint32_t cntv = count_v(st);
+    const uint32_t cnt = cntv * EPV;
+    if constexpr (!PIPE) load_step(st, v);
+    if (cntv == CAPV) {
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) lds[j * kStageThreads + t] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) {
+        const uint32_t i = j * kStageThreads + t;
+        if (i < cntv) lds[i] = v[j];
+      }
+    }
+    lds_barrier();
+    if constexpr (PIPE) {
+      // the next step's loads stay in flight while this one is computed and stored
+      if (st + gridDim.x < nsteps) load_step(st + gridDim.x, v);
+    }
+    const uint32_t nb = cnt >> (2 * K);
+    for (uint32_t b = t; b < nb; b += kStageThreads) {
+      S2* tb = le + ((b >> bpt_log) << (2 * m));
+      const uint32_t w = b & ((1u << bpt_log) - 1u);
+      const uint32_t p = deposit_free<K>(w >> F, g.ipos);
+      const uint32_t q = deposit_free<K>(w & ((1u << F) - 1u), g.ipos);
+      cd x[D * D];
+#pragma unroll
+      for (int u = 0; u < D; ++u)
+#pragma unroll
+        for (int vv = 0; vv < D; ++vv) {
+          const S2 e = tb[((p + dep_intra<K>(u, g.ipos)) << m) + q + dep_intra<K>(vv, g.ipos)];
+          x[u * D + vv] = cd{(double)e.x, (double)e.y};
+        }
+      block_apply<K, FORM>(x, cf, [&](int u, int vv, cd r) {
+        S2 e;
+        e.x = (T)r.re;
+        e.y = (T)r.im;
+        tb[((p + dep_intra<K>(u, g.ipos)) << m) + q + dep_intra<K>(vv, g.ipos)] = e;
+      });
+    }
+    lds_barrier();
+    u4* dst = hv + st * CAPV;
+    if (cntv == CAPV) {
+      u4 o[kStageVecs];
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) o[j] = lds[j * kStageThreads + t];
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) __builtin_nontemporal_store(o[j], dst + j * kStageThreads + t);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kStageVecs; ++j) {
+        const uint32_t i = j * kStageThreads + t;
+        if (i < cntv) __builtin_nontemporal_store(lds[i], dst + i);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- pair layout
 
 // Complex64 entries for the pair layout (ht_pair.h): single entries and
@@ -210,6 +468,90 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
+  // Lowest intra target (none: 99).  Automatic choices for complex128
+  // operators of 1 GiB and more, measured at n = 16 (TB/s of algorithmic
+  // traffic, before -> after): intra-tile passes staged through LDS in
+  // 128 KiB steps with the next step prefetched run every target at about
+  // 5.7 (4.9-5.6 before; two-qubit direct passes whose targets are all at
+  // bit 3 or above stay on the lane-patch kernel, 5.8 there); passes with a
+  // tile-selecting target take workgroup-wide steps of 16 waves, 4 groups
+  // per step (5.05-5.2 -> 5.2-5.35), two tile-selecting targets with
+  // row-run patches (interleave 0); an intra target below bit 3 beside a
+  // tile-selecting one stays on the lane-patch kernel (slower in steps).
+  constexpr int KI = K - C;
+  const int low = KI > 0 ? g.ipos[0] : 99;
+  if constexpr (C == 0) {
+    const uint64_t tile_bytes = (uint64_t)(2 * sizeof(T)) << (2 * g.m);
+    int stage = tuning().stage;
+    if (stage < 0) stage = (big && !(K == 2 && FORM == 0 && low >= 3)) ? 1 : 0;
+    const int sth = tuning().stage_threads;
+    const uint64_t step_bytes = 16ull * kStageVecs * (uint64_t)sth;
+    if (stage == 1 && tile_bytes <= step_bytes) {
+      const uint64_t steps_total = (nent * 2 * sizeof(T) + step_bytes - 1) / step_bytes;
+      uint64_t sw = (uint64_t)num_cu * (uint64_t)tuning().stage_wg_per_cu;
+      if (sw > steps_total) sw = steps_total;
+      const bool pipe = tuning().stage_pipe != 0;
+#define HT_STAGE(TH, P)                                                                                   \
+  hipLaunchKernelGGL((stage_kernel<T, K, FORM, TH, P>), dim3((unsigned)sw), dim3(TH), 0, s, hp, g, cf,   \
+                     coef_dev, nent)
+      if (sth == 512) {
+        if (pipe) HT_STAGE(512, true); else HT_STAGE(512, false);
+      } else {
+        if (pipe) HT_STAGE(256, true); else HT_STAGE(256, false);
+      }
+#undef HT_STAGE
+      return hipGetLastError();
+    }
+  }
+  // memory mode of the step kernels below (as for conj_kernel's automatic one)
+  int smode = tuning().mem_mode;
+  if (smode < 0) smode = (sizeof(T) == 8 && low >= 3) ? 3 : 0;
+  {
+    // workgroup steps with the next step prefetched (tuning only)
+    const int pw = tuning().pipe_waves;
+    if (pw > 0) {
+      const uint64_t items = g.ngroups * steps;
+      uint64_t wg = (items + pw - 1) / pw;
+      const uint64_t wcap = (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
+      if (wg > wcap) wg = wcap;
+#define HT_PIPE(M_, N_, B_) \
+  hipLaunchKernelGGL((conj_pipe_kernel<T, K, C, FORM, M_, N_, B_>), dim3((unsigned)wg), dim3(N_), 0, s, hp, g, cf, coef_dev)
+      const bool bar = tuning().pipe_barrier != 0;
+      if (pw == 8) {
+        if (smode == 3) HT_PIPE(3, 512, true); else HT_PIPE(0, 512, true);
+      } else if (bar) {
+        if (smode == 3) HT_PIPE(3, 256, true); else HT_PIPE(0, 256, true);
+      } else {
+        if (smode == 3) HT_PIPE(3, 256, false); else HT_PIPE(0, 256, false);
+      }
+#undef HT_PIPE
+      return hipGetLastError();
+    }
+  }
+  {
+    // workgroup-wide steps
+    int sw = tuning().sync_waves;
+    if (sw < 0) sw = (big && C > 0 && low >= 3) ? 16 : 0;
+    if (sw > 0) {
+      ConjGeom<K, C> gs = g;
+      int ilv = tuning().sync_interleave;
+      if (ilv < 0) ilv = C == 2 ? 0 : (use_interleave((int)sizeof(T) * 2) ? 1 : 0);
+      gs.ilv = ilv != 0;
+      const uint64_t wpb = (uint64_t)sw;
+      const uint64_t items = g.ngroups * steps;
+      uint64_t wg = (items + wpb - 1) / wpb;
+      const uint64_t wcap = (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
+      if (wg > wcap) wg = wcap;
+      const dim3 grid((unsigned)wg), block((unsigned)(64 * sw));
+      switch (smode) {
+        case 1: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 1>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
+        case 2: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 2>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
+        case 3: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 3>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
+        default: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 0>), grid, block, 0, s, hp, gs, cf, coef_dev);
+      }
+      return hipGetLastError();
+    }
+  }
   if constexpr (sizeof(T) == 4 && (K == 1 || FORM == 0)) {
     // The pair layout (k = 1, and k = 2 in the direct form) needs a free
     // column bit 0 and F >= 4.  Automatic use (pairs == 1) is limited to

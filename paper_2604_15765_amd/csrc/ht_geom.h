@@ -312,11 +312,14 @@ struct DirectMem {
     const V v = load_v(tb, off);
     return {(double)v.x, (double)v.y};
   }
-  // A loaded entry as a lane holds it until its block is computed: 8-byte
-  // entries stay in the storage type (half the registers, so twice the
-  // blocks in flight), 16-byte ones are kept as FP64 values, conjugated at
-  // once when read through a mirror.
-  static constexpr bool kNarrow = sizeof(T) == 4 && !WIDE;
+  // A loaded entry as a lane holds it until its block is computed: as stored
+  // (16-byte entries are FP64 values already; 8-byte ones take half the
+  // registers, so twice the blocks in flight), conjugated only when the block
+  // is widened.  Nothing is done to a loaded value before the block is
+  // computed, so all loads of a step stay in flight together (a conjugation
+  // at load time makes the compiler wait for every load at once).  WIDE
+  // converts 8-byte entries to FP64 (and conjugates) at load instead.
+  static constexpr bool kNarrow = sizeof(T) == 8 || !WIDE;
   struct Narrow {
     V v;
   };
@@ -369,7 +372,10 @@ HT_HD BlockPos block_pos(const ConjGeom<K, C>& g, const GroupCtx<C>& gc, uint32_
 
 // Read the block's 2^k x 2^k entries (row-major, local bits in ascending
 // target order); mirrored tiles are read transposed and their entries
-// conjugated (for 8-byte entries when the block is widened, block_widen).
+// conjugated (when the block is widened, block_widen).  Called for inactive
+// blocks too, which read the first entry of their tile instead: loads then
+// never sit behind a branch, so the compiler keeps a whole step of them in
+// flight (after a skipped load it could not count what is outstanding).
 template <int K, int C, typename Mem>
 HT_HD void block_load(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>& gc,
                       const BlockPos& bp, typename Mem::R (&x)[(1 << K) * (1 << K)]) {
@@ -386,7 +392,7 @@ HT_HD void block_load(const Mem& mem, const ConjGeom<K, C>& g, const GroupCtx<C>
       const int X = u >> KI, Y = v >> KI;
       const bool d = gc.dir[X][Y];
       const uint32_t off = d ? (ru << m) + cv : (cv << m) + ru;
-      x[u * D + v] = mem.load_x(gc.tbase[X][Y], off, !d);
+      x[u * D + v] = mem.load_x(gc.tbase[X][Y], bp.active ? off : 0u, !d);
     }
   }
 }
@@ -457,7 +463,7 @@ HT_HD void conj_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const GroupC
     for (int j = 0; j < JU; ++j) {
       const uint32_t b = (job + j) * 64u + lane;
       bp[j] = block_pos<K, C>(g, gc, b, job + j < job_end && b < nblk);
-      if (bp[j].active) block_load<K, C>(mem, g, gc, bp[j], x[j]);
+      block_load<K, C>(mem, g, gc, bp[j], x[j]);
     }
 #pragma unroll
     for (int j = 0; j < JU; ++j)

@@ -31,6 +31,18 @@ struct LaunchTuning {
   int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
   int pairs = 1;            // pair layout of complex64 passes (ht_pair.h): 0 off,
                             // 1 where it pays, 2 wherever it applies
+  int stage = -1;           // intra-tile passes staged through LDS in 64 KiB steps:
+                            // -1 automatic, 0 off, 1 wherever the tile fits
+  int stage_wg_per_cu = 1;  // workgroups per CU of the staged pass
+  int stage_pipe = 1;      // staged pass: prefetch the next step during compute
+  int stage_threads = 512;  // threads per workgroup of the staged pass (256: 64 KiB steps, 512: 128 KiB)
+  int sync_waves = -1;      // passes with a tile-selecting target in workgroup-wide
+                            // steps: -1 automatic, 0 off, else waves per workgroup (4, 8, 16)
+  int sync_wg_per_cu = 1;   // workgroups per CU of the synchronised pass
+  int sync_interleave = -1; // patch order of the synchronised pass: -1 automatic (0 for two
+                            // tile-selecting targets, else as "interleave"), 0 or 1
+  int pipe_waves = 0;       // steps with the next one prefetched: 0 off, 4 or 8 waves per workgroup
+  int pipe_barrier = 1;     // 4-wave prefetching workgroups meet at a barrier before each store phase
 };
 LaunchTuning& tuning();
 

@@ -180,6 +180,77 @@ def test_work_orders_give_bitwise_equal_results(ht):
         ht.set_tuning("native", 1)
 
 
+STEP_TUNINGS = [
+    # LDS-staged intra-tile pass: 64 and 128 KiB steps, with and without the prefetch
+    {"stage": 1, "stage_threads": 256, "stage_pipe": 1},
+    {"stage": 1, "stage_threads": 512, "stage_pipe": 1},
+    {"stage": 1, "stage_threads": 256, "stage_pipe": 0},
+    # workgroup-wide steps, both patch orders
+    {"sync_waves": 16},
+    {"sync_waves": 8, "sync_interleave": 0},
+    {"sync_waves": 4, "sync_interleave": 1},
+    # steps with the next one prefetched, with and without the barrier
+    {"pipe_waves": 4},
+    {"pipe_waves": 4, "pipe_barrier": 0},
+    {"pipe_waves": 8},
+]
+STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
+                 "pipe_waves": 0, "pipe_barrier": 1, "native": 1}
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_step_kernels_give_bitwise_equal_results(ht, dtype):
+    """The LDS-staged intra-tile pass, the workgroup-wide step kernels and
+    the prefetching ones apply the same block arithmetic (Eq. (2) direct,
+    Eq. (3) transfer) to the same blocks as the lane-patch kernel: bitwise
+    equal storage for every class, at tile edges 8 (the staged pass's last
+    step is then partial) and 32, against the lane-patch kernel (all of
+    them off), and the result matches the oracle."""
+    rng = synth.make_rng(471)
+    n = 9
+    H = synth.random_hermitian_dense(n, rng)
+    ops = []
+    for _ in range(24):
+        k = int(rng.integers(1, 3))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        c = rng.random()
+        mats = (synth.haar_unitary(1 << k, rng)[None] if c < 0.5 else synth.random_kraus_set(k, 2, rng))
+        ops.append((t, mats))
+    # every class at least once: intra (low and high bits), one and two tile-selecting targets
+    ops += [([0], synth.haar_unitary(2, rng)[None]), ([2, 1], synth.haar_unitary(4, rng)[None]),
+            ([4, 3], synth.random_kraus_set(2, 3, rng)), ([8], synth.haar_unitary(2, rng)[None]),
+            ([6, 1], synth.haar_unitary(4, rng)[None]), ([8, 6], synth.haar_unitary(4, rng)[None]),
+            ([7, 5], synth.random_kraus_set(2, 2, rng))]
+    want = oracle.apply_ops(H, [synth.random_ops.channel_op(t, mats) for t, mats in ops])
+
+    def run(tune, m):
+        for k, v in STEP_DEFAULTS.items():
+            ht.set_tuning(k, v)
+        ht.set_tuning("native", 0)
+        ht.set_tuning("stage", 0)
+        ht.set_tuning("sync_waves", 0)
+        for k, v in tune.items():
+            ht.set_tuning(k, v)
+        h = make(ht, n, m, H, dtype)
+        for t, mats in ops:
+            h.apply_channel(t, mats)
+        raw, dense = h.raw_entries(), h.to_dense()
+        h.close()
+        return raw, dense
+
+    try:
+        for m in (3, 5):
+            base, dense = run({}, m)
+            tol = 1e-12 if dtype == "c128" else 4e-5
+            assert rel(dense, want) <= tol, (m, rel(dense, want))
+            for tune in STEP_TUNINGS:
+                raw, _ = run(tune, m)
+                assert np.array_equal(base, raw), (m, tune)
+    finally:
+        for k, v in STEP_DEFAULTS.items():
+            ht.set_tuning(k, v)
+
+
 def test_native_gate_exactness(ht):
     """X twice is the identity bitwise; CNOT leaves the control-0 quarter
     bitwise unchanged; S leaves entries with equal target bits unchanged."""
