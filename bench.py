@@ -54,10 +54,12 @@ def parse():
     p.add_argument("--no-c64", action="store_true",
                    help="skip the complex64-storage run of the same steps (run only with --dtype c128)")
     p.add_argument("--no-serve", action="store_true", help="skip the served-requests run")
-    p.add_argument("--serve-count", type=int, default=48, help="requests of the served-requests run")
-    p.add_argument("--serve-rate", type=float, default=1000.0, help="Poisson arrival rate (/s) of that run")
-    p.add_argument("--cpu-sample-n", type=int, default=12,
-                   help="qubits of the dense sub-operator the CPU oracle is timed on")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-operators run")
+    p.add_argument("--batched-count", type=int, default=4096, help="operators of the batched run")
+    p.add_argument("--batched-per-n", type=int, default=32,
+                   help="operators per n of the batched run checked against the oracle")
+    p.add_argument("--serve-count", type=int, default=256, help="requests per rate of the served-requests run")
+    p.add_argument("--serve-rates", default="100,1000", help="Poisson arrival rates (/s) of that run")
     p.add_argument("--tune", action="append", default=[], metavar="NAME=VALUE",
                    help="launch tuning passed to ht_set_tuning (repeatable)")
     p.add_argument("--copy-only", action="store_true",
@@ -70,46 +72,63 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_full: int, n_sample: int, seed: int) -> dict:
-    """Time the CPU oracle on a bounded sample of the workload.
-
-    Sample: the 2^s x 2^s sub-operator (s = n_sample) that fixing the top
-    n_full - s qubits selects, evolved by two layers of the same op mix on its s
-    qubits (a k-local op on those qubits maps that sub-operator to itself), with
-    the oracle's Eq. (2) block form over the dense matrix.  The oracle's cost is
-    proportional to the number of entries, so the per-op time is scaled by
-    4^(n_full - s) to the full operator.  Reported as conjugation passes/s."""
+def _oracle_per_op(n_full: int, n_sample: int, seed: int, budget_s: float) -> dict:
+    """Per-op time of the CPU oracle (Eq. (2) block form, numpy complex128)
+    on the 2^s x 2^s sub-operator (s = n_sample) that fixing the top
+    n_full - s qubits selects -- a k-local op on the low s qubits maps it to
+    itself -- over ops drawn in random order from two layers of the benchmark's
+    op mix on those s qubits, until `budget_s` seconds have passed."""
     import oracle
     import synth
+    rng = synth.make_rng(seed)
+    G = synth.ginibre_factor(n_sample, 16, rng)
+    rho = oracle.density_from_factor(G)
+    ops = synth.layer_n16(0, rng, n=n_sample) + synth.layer_n16(1, rng, n=n_sample)
+    order = rng.permutation(len(ops))
+    t0 = time.perf_counter()
+    done = 0
+    for i in order:
+        op = ops[int(i)]
+        rho = oracle.local_block_map(rho, op.mats, op.targets)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"n_sample": n_sample, "ops": done, "seconds": dt, "per_op_s": dt / done,
+            "gate_conj_per_s_at_sample_size": done / dt}
+
+
+def cpu_baseline(n_full: int, seed: int) -> dict:
+    """Time the CPU oracle on a bounded sample of the workload.
+
+    Measured at n = 14 (the largest size whose dense 4 GiB matrix the oracle
+    handles on a host in seconds per op): the per-op time there, scaled by
+    4^(n_full - 14) to the full operator (the oracle's cost is proportional to
+    the number of entries), gives the reported passes/s.  A second sample at
+    n = 12, scaled by 4^(n_full - 12), is reported beside it."""
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    rng = synth.make_rng(seed)
-    G = synth.ginibre_factor(n_sample, 16, rng)
-    rho = oracle.density_from_factor(G)
-    ops = synth.layer_n16(0, rng, n=n_sample) + synth.layer_n16(1, rng, n=n_sample)
-    t0 = time.perf_counter()
-    done = 0
-    for op in ops:
-        rho = oracle.local_block_map(rho, op.mats, op.targets)
-        done += 1
-        if time.perf_counter() - t0 > 25.0:
-            break
-    dt = time.perf_counter() - t0
-    per_op_sample = dt / done
-    per_op_full = per_op_sample * 4.0 ** (n_full - n_sample)
+    main_n = min(14, n_full)
+    m = _oracle_per_op(n_full, main_n, seed, 25.0)
+    sec = _oracle_per_op(n_full, min(12, n_full), seed + 1, 8.0)
+    scale = 4.0 ** (n_full - main_n)
     return {
-        "value": 1.0 / per_op_full,
+        "value": 1.0 / (m["per_op_s"] * scale),
         "unit": "gate-conj/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle Eq.(2) block form (numpy complex128) on the {1 << n_sample}x{1 << n_sample} "
-                   f"sub-operator of the n={n_full} state with the top {n_full - n_sample} qubits fixed, "
-                   f"{done} ops of two layers of the same mix on its {n_sample} qubits in {dt:.1f} s; "
-                   f"per-op time scaled by 4^{n_full - n_sample} to n={n_full}"),
-        "seconds": dt,
+        "sample": (f"oracle Eq.(2) block form (numpy complex128) on the {1 << main_n}x{1 << main_n} "
+                   f"sub-operator of the n={n_full} state with the top {n_full - main_n} qubits fixed, "
+                   f"{m['ops']} ops drawn at random from two layers of the same mix on its {main_n} qubits "
+                   f"in {m['seconds']:.1f} s ({m['per_op_s']:.2f} s per op); per-op time scaled by "
+                   f"4^{n_full - main_n} to n={n_full}"),
+        "seconds": m["seconds"],
+        "measured": m,
+        "secondary_n12": {**sec, "scaled_gate_conj_per_s": 1.0 / (sec["per_op_s"] * 4.0 ** (n_full - sec["n_sample"]))},
+        "host_cores": len(os.sched_getaffinity(0)),
     }
 
 
@@ -202,16 +221,157 @@ def fused_run(ht, h, G, layers, args, codes, coeffs, tr_plain, ev_plain) -> dict
     }
 
 
-def serve_run(ht, count: int, rate: float, seed: int) -> dict:
-    """The served half of the metric: a Poisson stream of `count` requests
-    (n log-uniform in 6..16, 10..300 mixed ops, c128/c64, half with a 64-term
-    Pauli-sum readout; the stream `bench_ext.py serve` sweeps) served by the
-    continuous-batching server and by the plain one-at-a-time baseline on the
-    same requests: circuits/s and p50/p99 latency (arrival to result)."""
+def batched_run(ht, count: int, per_n: int, seed: int) -> dict:
+    """The batched extension on its own workload: `count` independent
+    operators, n ~ U{4..11}, each a normalised Ginibre state of rank
+    min(2^n, 64) under its own U{20..64}-op random noisy circuit (Haar 1q/2q,
+    depolarising/dephasing), evolved (1) with one launch per op, (2) in one
+    persistent batched launch, (3) in one batched launch with the launch
+    shape and tile edge per n picked by the autotuner, and (4) the same with
+    each operator's ops fused into 2-qubit passes.  Final states: (2) and (3)
+    bitwise against one launch per op at the same tile edges, (4) against (3);
+    a stratified sample (`per_n` operators per n) against the CPU oracle's
+    block form, whose time on the host's cores is reported as its rate."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
     import synth
-    reqs = synth.serving_requests(count, rate, seed=seed)
 
-    def stream(**cfg):
+    rngs = synth.spawn_rngs(seed, count)
+    work = []
+    for rng in rngs:
+        n = int(rng.integers(4, 12))
+        G = synth.ginibre_factor(n, min(1 << n, 64), rng)
+        ops = [synth.circuits._random_mixed_op(n, rng, "dephase") for _ in range(int(rng.integers(20, 65)))]
+        work.append((n, G, ops))
+    nops = sum(len(w[2]) for w in work)
+    G_dev = [torch.from_numpy(G).to("cuda") for _, G, _ in work]
+    default_edges = {n: 5 for n in range(4, 12)}
+
+    def fresh(edges):
+        hs = []
+        for (n, _, _), g in zip(work, G_dev):
+            h = ht.Herm(n, edges[n]).init_lowrank(g)
+            h.scale(1.0 / h.trace())
+            hs.append(h)
+        torch.cuda.synchronize()
+        return hs
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def run_plain(hs):
+        for h, (_, _, ops) in zip(hs, work):
+            for op in ops:
+                h.apply_op(op)
+
+    def queue(hs, **params):
+        b = ht.Batch(**params)
+        for h, (_, _, ops) in zip(hs, work):
+            for op in ops:
+                b.add_op(h, op)
+        return b
+
+    plain = fresh(default_edges)
+    t_plain = timed(lambda: run_plain(plain))
+    batched = fresh(default_edges)
+    b = queue(batched, threads=256, wg_per_cu=2)
+    t_batch = timed(b.run)
+    same_batch = all(torch.equal(x.buffer, y.buffer) for x, y in zip(plain, batched))
+    del plain
+    log(f"[bench] batched: plain {t_plain:.3f} s, one batched launch {t_batch:.3f} s")
+    cfg = b.autotune(512)
+    b.close()
+    edges = dict(default_edges)
+    edges.update(cfg["tile_log2"])
+    tplain = fresh(edges)
+    t_tplain = timed(lambda: run_plain(tplain))
+    tuned = fresh(edges)
+    tb = queue(tuned, threads=cfg["threads"], wg_per_cu=cfg["wg_per_cu"], lds_max_bytes=cfg["lds_max_bytes"])
+    t_tuned = timed(tb.run)
+    tb.close()
+    same_tuned = all(torch.equal(x.buffer, y.buffer) for x, y in zip(tplain, tuned))
+    del tplain
+    fused = fresh(edges)
+    fb = queue(fused, threads=cfg["threads"], wg_per_cu=cfg["wg_per_cu"], lds_max_bytes=cfg["lds_max_bytes"],
+               fuse_qubits=2)
+    t_fused_plan = timed(fb.run)  # host planning and composition of every operator's passes, then the launch
+    fused_dev = max(float(np.linalg.norm(x.to_dense() - y.to_dense()) / np.linalg.norm(y.to_dense()))
+                    for x, y, (n, _, _) in zip(fused, tuned, work) if n <= 8)
+    # oracle on the stratified sample, operators spread over the host's cores
+    sample, seen = [], {}
+    for i, (n, _, _) in enumerate(work):
+        if seen.get(n, 0) < per_n:
+            seen[n] = seen.get(n, 0) + 1
+            sample.append(i)
+    cores = len(os.sched_getaffinity(0))
+
+    def ref(i):
+        n, G, ops = work[i]
+        return oracle.apply_ops_local(oracle.density_from_factor(G), ops)
+
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except Exception:
+        limit = None
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        refs = list(ex.map(ref, sample))
+    t_oracle = time.perf_counter() - t0
+    if limit is not None:
+        limit.restore_original_limits()
+    worst = {"batched": 0.0, "tuned": 0.0, "fused": 0.0}
+    for i, r in zip(sample, refs):
+        nr = np.linalg.norm(r)
+        for name, hs in (("batched", batched), ("tuned", tuned), ("fused", fused)):
+            worst[name] = max(worst[name], float(np.linalg.norm(hs[i].to_dense() - r) / nr))
+    # the same fused batch again: plans cached, device time plus table upload
+    # (the operators now hold the circuits applied twice; nothing is compared after this)
+    t_fused = timed(fb.run)
+    fb.close()
+    log(f"[bench] batched: tuned {t_tuned:.3f} s (plain at the tuned edges {t_tplain:.3f} s), "
+        f"fused {t_fused:.3f} s ({t_fused_plan:.3f} s with planning)")
+    oracle_ops = sum(len(work[i][2]) for i in sample)
+    log(f"[bench] batched: oracle on {len(sample)} operators in {t_oracle:.1f} s, max errors {worst}")
+    for hs in (batched, tuned, fused):
+        for h in hs:
+            h.close()
+    return {
+        "operators": count, "ops": nops, "unit": "circuits/s",
+        "workload": "n ~ U{4..11}, Ginibre rank min(2^n, 64), U{20..64} ops each: 50% Haar 1q, 30% Haar 2q, "
+                    "20% 1q depolarising/dephasing p ~ U(0, 0.1)",
+        "plain_launches": {"s": t_plain, "circuits_per_s": count / t_plain, "gate_conj_per_s": nops / t_plain},
+        "batched_launch": {"s": t_batch, "circuits_per_s": count / t_batch, "gate_conj_per_s": nops / t_batch,
+                           "speedup_vs_plain": t_plain / t_batch, "bitwise_equal_to_plain": same_batch},
+        "autotuned": {"s": t_tuned, "circuits_per_s": count / t_tuned, "config": cfg,
+                      "plain_launches_same_edges_s": t_tplain, "speedup_vs_plain": t_plain / t_tuned,
+                      "bitwise_equal_to_plain_same_edges": same_tuned},
+        "fused": {"s": t_fused, "s_with_host_planning": t_fused_plan,
+                  "circuits_per_s": count / t_fused, "speedup_vs_plain": t_plain / t_fused,
+                  "max_rel_frobenius_vs_unfused_n_le_8": fused_dev},
+        "oracle_check": {"operators": len(sample), "per_n": per_n, "max_rel_frobenius": worst,
+                         "tolerance": 1e-12, "oracle_s": t_oracle, "oracle_threads": cores,
+                         "oracle_circuits_per_s": len(sample) / t_oracle,
+                         "oracle_gate_conj_per_s": oracle_ops / t_oracle},
+    }
+
+
+def serve_run(ht, count: int, rates, seed: int) -> dict:
+    """The served half of the metric: Poisson streams of `count` requests
+    (n log-uniform in 6..16, 10..300 mixed ops, c128/c64, half with a 64-term
+    Pauli-sum readout) at each arrival rate, served four ways on the same
+    requests -- one at a time (the plain baseline), with continuous batching,
+    and both again with each request's ops fused into 2-qubit passes -- so
+    that batching and fusion are measured apart: circuits/s and p50/p99
+    latency (arrival to result)."""
+    import synth
+
+    def stream(reqs, **cfg):
         srv = ht.Server(**cfg)
         t_start = srv.now()
         ids = []
@@ -225,27 +385,48 @@ def serve_run(ht, count: int, rate: float, seed: int) -> dict:
         recs = [res[i] for i in ids]
         lat = np.array([d["t_done"] - d["t_submit"] for d in recs])
         span = max(d["t_done"] for d in recs) - min(d["t_submit"] for d in recs)
+        busy = np.array([d["t_done"] - d["t_admit"] for d in recs])
+        big = np.array([r["n"] >= 14 for r in reqs])
         return ({"circuits_per_s": len(recs) / span, "p50_s": float(np.percentile(lat, 50)),
-                 "p99_s": float(np.percentile(lat, 99)),
-                 "failed": sum(1 for d in recs if d["status"] != 0)}, [d["value"] for d in recs])
+                 "p99_s": float(np.percentile(lat, 99)), "makespan_s": span,
+                 "failed": sum(1 for d in recs if d["status"] != 0),
+                 # one at a time, a request's admit-to-done time is its service time
+                 "service_share_n_ge_14": float(busy[big].sum() / busy.sum())},
+                [d["value"] for d in recs])
 
-    cont, v_cont = stream()
-    log(f"[bench] served (continuous batching): {cont}")
-    fused, v_fused = stream(fuse_qubits=2)
-    log(f"[bench] served (continuous batching, each request's ops fused into 2-qubit passes): {fused}")
-    fifo, v_fifo = stream(fifo=1)
-    log(f"[bench] served (one at a time): {fifo}")
-    return {
-        "requests": count, "rate_per_s": rate, "ops": sum(len(r["ops"]) for r in reqs),
-        "unit": "circuits/s", "continuous": cont, "continuous_fused": fused, "plain_fifo": fifo,
-        "throughput_ratio": cont["circuits_per_s"] / fifo["circuits_per_s"],
-        "p99_ratio": fifo["p99_s"] / cont["p99_s"],
-        "p50_ratio": fifo["p50_s"] / cont["p50_s"],
-        "fused_throughput_ratio": fused["circuits_per_s"] / fifo["circuits_per_s"],
-        "fused_p99_ratio": fifo["p99_s"] / fused["p99_s"],
-        "results_bitwise_equal": v_cont == v_fifo,
-        "fused_max_rel_dev": max(abs(a - b) / max(1.0, abs(b)) for a, b in zip(v_fused, v_fifo)),
-    }
+    out = {"requests_per_rate": count, "unit": "circuits/s", "rates": {}}
+    for rate in rates:
+        reqs = synth.serving_requests(count, rate, seed=seed)
+        legs, vals = {}, {}
+        for name, cfg in (("plain_fifo", {"fifo": 1}), ("continuous", {}),
+                          ("fused_fifo", {"fifo": 1, "fuse_qubits": 2}), ("continuous_fused", {"fuse_qubits": 2})):
+            legs[name], vals[name] = stream(reqs, **cfg)
+            if name.startswith("continuous"):
+                legs[name].pop("service_share_n_ge_14")
+            log(f"[bench] served at {rate:g}/s, {name}: {legs[name]}")
+        f, c, ff, cf = legs["plain_fifo"], legs["continuous"], legs["fused_fifo"], legs["continuous_fused"]
+        out["rates"][f"{rate:g}"] = {
+            "ops": sum(len(r["ops"]) for r in reqs),
+            "n_ge_14_requests": sum(1 for r in reqs if r["n"] >= 14),
+            **legs,
+            # batching alone: continuous vs one at a time, unfused and fused
+            "batching_throughput_ratio": c["circuits_per_s"] / f["circuits_per_s"],
+            "batching_p99_ratio": f["p99_s"] / c["p99_s"],
+            "batching_p50_ratio": f["p50_s"] / c["p50_s"],
+            "batching_throughput_ratio_fused": cf["circuits_per_s"] / ff["circuits_per_s"],
+            "batching_p99_ratio_fused": ff["p99_s"] / cf["p99_s"],
+            "batching_p50_ratio_fused": ff["p50_s"] / cf["p50_s"],
+            # fusion alone, one at a time; and both against the plain baseline
+            "fusion_throughput_ratio": ff["circuits_per_s"] / f["circuits_per_s"],
+            "combined_throughput_ratio": cf["circuits_per_s"] / f["circuits_per_s"],
+            "combined_p99_ratio": f["p99_s"] / cf["p99_s"],
+            "results_bitwise_equal_continuous_vs_fifo": vals["continuous"] == vals["plain_fifo"],
+            "results_bitwise_equal_fused_continuous_vs_fused_fifo":
+                vals["continuous_fused"] == vals["fused_fifo"],
+            "fused_max_rel_dev_vs_plain": max(abs(a - b) / max(1.0, abs(b))
+                                              for a, b in zip(vals["continuous_fused"], vals["plain_fifo"])),
+        }
+    return out
 
 
 def main():
@@ -380,13 +561,18 @@ def main():
         out["complex64"] = c64_run(ht, G, layers, args, codes, coeffs, tr, ev)
     if not args.no_fused:
         out["fused"] = fused_run(ht, h, G, layers, args, codes, coeffs, tr, ev)
-    if not args.no_serve:
+    if not args.no_serve or not args.no_batched:
         h.close()
         torch.cuda.empty_cache()
-        out["serving"] = serve_run(ht, args.serve_count, args.serve_rate, args.seed)
+    if not args.no_batched:
+        out["batched"] = batched_run(ht, args.batched_count, args.batched_per_n, 4096)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = serve_run(ht, args.serve_count, [float(x) for x in args.serve_rates.split(",")],
+                                   args.seed)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(n, min(args.cpu_sample_n, n), args.seed)
+        out["cpu_baseline"] = cpu_baseline(n, args.seed)
     print(json.dumps(out), flush=True)
 
 
