@@ -54,6 +54,12 @@ def parse():
     p.add_argument("--no-c64", action="store_true",
                    help="skip the complex64-storage run of the same steps (run only with --dtype c128)")
     p.add_argument("--no-serve", action="store_true", help="skip the served-requests run")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the launch-shape tuning of the passes (ht_tune_passes) before timing")
+    p.add_argument("--tuned-shapes-out", help="write the tuned pass shapes (JSON) to this file")
+    p.add_argument("--tuned-shapes-in",
+                   help="apply the pass shapes of this file (written by --tuned-shapes-out) instead of tuning")
+    p.add_argument("--tune-only", action="store_true", help="stop after tuning (with --tuned-shapes-out)")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-operators run")
     p.add_argument("--batched-count", type=int, default=4096, help="operators of the batched run")
     p.add_argument("--batched-per-n", type=int, default=32,
@@ -141,6 +147,12 @@ def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128) -> dict:
     h = ht.Herm(args.n, args.tile_log2, "c64")
     h.init_lowrank(G)
     h.scale(1.0 / h.trace())
+    if args.tuned_shapes_in:
+        with open(args.tuned_shapes_in) as fh:
+            for r in json.load(fh).get("c64", []):
+                ht.set_pass_shape("c64", args.n, args.tile_log2, r)
+    elif not args.no_tune:
+        h.tune_passes(2)
     for l in range(args.warmup):
         for op in layers[l]:
             h.apply_op(op)
@@ -476,6 +488,30 @@ def main():
     h.init_lowrank(G)
     h.scale(1.0 / h.trace())
     torch.cuda.synchronize()
+    # launch shapes per pass class timed on this operator (identity passes:
+    # the state is unchanged), outside the timed region
+    t0 = time.perf_counter()
+    if args.tuned_shapes_in:
+        with open(args.tuned_shapes_in) as fh:
+            tuned = json.load(fh)[args.dtype]
+        for r in tuned:
+            ht.set_pass_shape(args.dtype, n, m, r)
+    else:
+        tuned = [] if args.no_tune else h.tune_passes(2)
+    tune_s = time.perf_counter() - t0
+    for r in tuned:
+        log(f"[bench] pass shape {r}")
+    if args.tuned_shapes_out:
+        shapes = {args.dtype: tuned}
+        if args.dtype == "c128" and not args.no_c64:
+            h64 = ht.Herm(n, m, "c64")
+            h64.init_lowrank(G)
+            shapes["c64"] = h64.tune_passes(2)
+            h64.close()
+        with open(args.tuned_shapes_out, "w") as fh:
+            json.dump(shapes, fh, indent=1)
+    if args.tune_only:
+        return
 
     def step(ops):
         for op in ops:
@@ -536,6 +572,9 @@ def main():
                          f"Haar U(4), amplitude damping 0.01 on all qubits) + trace + 64-term Pauli sum"),
             "n": n, "tile_edge": 1 << h.tile_log2, "storage": args.dtype,
             "ops_per_step": nops / args.steps, "storage_bytes": h.nbytes, "tuning": tuning,
+            "tuned_shapes": {f"k{r['k']}_c{r['cross']}_{r['form']}{'_low' if r['low_intra'] else ''}": r["shape"]
+                             for r in tuned},
+            "tune_s": tune_s,
         },
         "hbm_GBps": nops * per_op_bytes / elapsed / 1e9,
         # the paper's effective bandwidth: stored bytes / time per op (one direction)

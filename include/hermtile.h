@@ -542,6 +542,40 @@ const char* ht_kernel_class_name(int idx);
  * while no other thread enqueues work (a server's scheduler thread reads it). */
 ht_status ht_set_tuning(const char* name, int64_t value);
 
+/* Launch-shape tuning of the conjugation pass by measurement on h.  The pass
+ * streams every stored entry from and to HBM (Algorithms 2 and 3); which
+ * launch shape streams fastest differs by a few percent between devices.
+ * For every pass class of h's shape (storage type, n, tile edge) -- k = 1
+ * and 2 targets, 0 to 2 of them tile-selecting, direct and transfer form,
+ * an intra target below bit 3 or not -- this times each candidate shape
+ * (the lane-patch kernel; the LDS-staged intra-tile pass or 16-wave
+ * workgroup steps at grids of 1, 3/4 and 5/8 workgroups per CU) on identity
+ * passes of h, reps timed rounds after one warm-up round, and keeps the
+ * fastest for operators of that shape.  The choice is process-wide and is
+ * used while the launch tuning (ht_set_tuning "stage", "sync_waves",
+ * "pipe_waves") is automatic; every shape computes bitwise the same result.
+ * The identity passes leave every represented entry of h unchanged (a
+ * negative zero may become a positive one, and the stored upper halves of
+ * diagonal tiles are rewritten as the conjugates of the lower ones, which
+ * is the same matrix).  Synchronises h's stream; at n = 16 it takes about
+ * 3 s.  rows (host, may be NULL when max_rows = 0): up to max_rows records
+ * of 7 doubles per class: k, tile-selecting targets, form (0 direct, 1
+ * transfer), low (1: an intra target below bit 3), chosen shape (0 lane
+ * patch, 1-3 staged at 1, 3/4, 5/8 workgroups per CU, 4-6 workgroup steps
+ * at the same grids), its ms per pass, the lane-patch kernel's ms per pass;
+ * nrows (may be NULL): classes tuned.  HT_EINVAL for a NULL handle, reps
+ * outside [1, 16] or rows NULL with max_rows > 0.  Call it while no other
+ * thread enqueues passes (it switches the process-wide launch tuning). */
+ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* rows, int* nrows);
+
+/* Set the launch shape of one pass class on operators of the given storage
+ * type, n and tile edge, as ht_tune_passes would (for example from the
+ * records of an earlier ht_tune_passes run; k, cross, form, low and shape as
+ * in those records); shape -1 returns the class to the automatic choice.  No
+ * GPU work.  HT_EINVAL for a class the operator shape cannot have, a staged
+ * shape with a tile-selecting target or a step shape without one. */
+ht_status ht_set_pass_shape(int dtype, int n, int tile_log2, int k, int cross, int form, int low, int shape);
+
 /* Pure host function (no GPU): the per-op preparation the library performs
  * before a launch, exposed for testing.  Given the same arguments as
  * ht_apply_channel (r = 1 for a unitary) and an operator shape (n, tile_log2),

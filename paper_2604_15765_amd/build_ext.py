@@ -31,7 +31,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 LIB_SOURCES = ["ht_conj.hip", "ht_native.hip", "ht_k3.hip", "ht_misc.hip", "ht_batch.hip", "ht_api.cpp",
                "ht_batch_api.cpp", "ht_circuit.cpp", "ht_batch_runner.cpp", "ht_autotune.cpp",
-               "ht_fuse.cpp", "ht_server.cpp", "ht_prep.cpp", "ht_noalloc.hip"]
+               "ht_fuse.cpp", "ht_server.cpp", "ht_prep.cpp", "ht_noalloc.hip",
+               "ht_tune.cpp"]
 LIB = os.path.join(HERE, "libhermtile.so")
 HOSTCHECK = os.path.join(HERE, "_hostcheck.so")
 PROBE = os.path.join(HERE, "_probe.so")

@@ -629,6 +629,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().stage_wg_per_cu = (int)value;
     return HT_OK;
   }
+  if (k == "stage_grid" || k == "sync_grid") {
+    if (value < 0 || value > 65536) return ht_fail(HT_EINVAL, "%s must be in [0, 65536]", name);
+    (k == "stage_grid" ? ht::tuning().stage_grid : ht::tuning().sync_grid) = (int)value;
+    return HT_OK;
+  }
   if (k == "stage_pipe") {
     if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "stage_pipe must be 0 or 1");
     ht::tuning().stage_pipe = (int)value;

@@ -480,15 +480,23 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   // tile-selecting one stays on the lane-patch kernel (slower in steps).
   constexpr int KI = K - C;
   const int low = KI > 0 ? g.ipos[0] : 99;
+  // a shape the pass tuner picked for this class and operator shape, used
+  // while the launch tuning is automatic
+  int shape = -1;
+  if (tuning().stage < 0 && tuning().sync_waves < 0 && tuning().pipe_waves == 0)
+    shape = tuned_shape(sizeof(T) == 8 ? 0 : 1, n, g.m, K, C, FORM, low < 3 ? 1 : 0);
   if constexpr (C == 0) {
     const uint64_t tile_bytes = (uint64_t)(2 * sizeof(T)) << (2 * g.m);
     int stage = tuning().stage;
     if (stage < 0) stage = (big && !(K == 2 && FORM == 0 && low >= 3)) ? 1 : 0;
+    if (shape >= 0) stage = (shape >= kShapeStage && shape <= kShapeStage58) ? 1 : 0;
     const int sth = tuning().stage_threads;
     const uint64_t step_bytes = 16ull * kStageVecs * (uint64_t)sth;
     if (stage == 1 && tile_bytes <= step_bytes) {
       const uint64_t steps_total = (nent * 2 * sizeof(T) + step_bytes - 1) / step_bytes;
-      uint64_t sw = (uint64_t)num_cu * (uint64_t)tuning().stage_wg_per_cu;
+      uint64_t sw = tuning().stage_grid > 0 ? (uint64_t)tuning().stage_grid
+                                            : (uint64_t)num_cu * (uint64_t)tuning().stage_wg_per_cu;
+      if (shape >= 0) sw = shape_grid(shape, num_cu);
       if (sw > steps_total) sw = steps_total;
       const bool pipe = tuning().stage_pipe != 0;
 #define HT_STAGE(TH, P)                                                                                   \
@@ -531,7 +539,8 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   {
     // workgroup-wide steps
     int sw = tuning().sync_waves;
-    if (sw < 0) sw = (big && C > 0 && low >= 3) ? 16 : 0;
+    if (sw < 0) sw = (big && C > 0 && low >= 3 && !(K == 2 && C == 1)) ? 16 : 0;
+    if (shape >= 0) sw = (C > 0 && shape >= kShapeSync && shape <= kShapeSync58) ? 16 : 0;
     if (sw > 0) {
       ConjGeom<K, C> gs = g;
       int ilv = tuning().sync_interleave;
@@ -540,7 +549,9 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       const uint64_t wpb = (uint64_t)sw;
       const uint64_t items = g.ngroups * steps;
       uint64_t wg = (items + wpb - 1) / wpb;
-      const uint64_t wcap = (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
+      uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
+                                             : (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
+      if (shape >= 0) wcap = shape_grid(shape, num_cu);
       if (wg > wcap) wg = wcap;
       const dim3 grid((unsigned)wg), block((unsigned)(64 * sw));
       switch (smode) {

@@ -34,6 +34,8 @@ struct LaunchTuning {
   int stage = -1;           // intra-tile passes staged through LDS in 64 KiB steps:
                             // -1 automatic, 0 off, 1 wherever the tile fits
   int stage_wg_per_cu = 1;  // workgroups per CU of the staged pass
+  int stage_grid = 0;       // staged pass: workgroups of the grid (0: stage_wg_per_cu per CU)
+  int sync_grid = 0;        // synchronised pass: workgroups of the grid (0: sync_wg_per_cu per CU)
   int stage_pipe = 1;      // staged pass: prefetch the next step during compute
   int stage_threads = 512;  // threads per workgroup of the staged pass (256: 64 KiB steps, 512: 128 KiB)
   int sync_waves = -1;      // passes with a tile-selecting target in workgroup-wide
@@ -45,6 +47,30 @@ struct LaunchTuning {
   int pipe_barrier = 1;     // 4-wave prefetching workgroups meet at a barrier before each store phase
 };
 LaunchTuning& tuning();
+
+// Launch shapes of the conjugation pass that the pass tuner (ht_tune_passes)
+// chooses between for a class of passes.  Every shape computes the same
+// blocks with the same arithmetic (bitwise equal results).
+enum PassShape {
+  kShapeLane = 0,      // lane-patch kernel (conj_kernel), automatic grid
+  kShapeStage = 1,     // LDS-staged intra-tile pass, grid: one workgroup per CU
+  kShapeStage34 = 2,   //   ... three workgroups per four CUs
+  kShapeStage58 = 3,   //   ... five per eight
+  kShapeSync = 4,      // 16-wave workgroup-wide steps, one workgroup per CU
+  kShapeSync34 = 5,
+  kShapeSync58 = 6,
+  kShapeCount = 7
+};
+// Grid of a shape: workgroups for num_cu compute units.
+inline uint64_t shape_grid(int shape, int num_cu) {
+  const int f = (shape == kShapeStage34 || shape == kShapeSync34) ? 6 : (shape == kShapeStage58 || shape == kShapeSync58) ? 5 : 8;
+  return (uint64_t)num_cu * (uint64_t)f / 8u;
+}
+// The tuned shape of a pass class on operators of this storage type and
+// shape (n, effective tile exponent m); low: an intra target lies below
+// bit 3.  -1 when none has been tuned.
+int tuned_shape(int dtype, int n, int m, int k, int c, int form, int low);
+void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int shape);
 
 // Workgroups per CU for a kernel family: the tuning value if set, else the
 // family's measured default auto_value.

@@ -45,15 +45,21 @@ def _csv(d, suffix):
 
 
 def kernel_class(name: str):
-    """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct',
+    """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct' (also the
+    workgroup-step kernels conj_sync_kernel and conj_pipe_kernel),
+    'stage_kernel<double, 2, 1, 512, true>' -> 'c128_k2_c0_transfer',
     'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
     'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus',
     'pair_kernel<1, 1, 0, 3, 2>' -> 'c64_k1_c1_direct' (complex64 only); None
     otherwise."""
-    m = re.search(r"conj_kernel<(double|float), (\d), (\d), (\d), (\d)>", name)
+    m = re.search(r"conj_(?:sync_|pipe_)?kernel<(double|float), (\d), (\d), (\d), (\d)", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k{m.group(2)}_c{m.group(3)}_{'direct' if m.group(4) == '0' else 'transfer'}"
+    m = re.search(r"stage_kernel<(double|float), (\d), (\d), \d+, (?:true|false)>", name)
+    if m:
+        dt = "c128" if m.group(1) == "double" else "c64"
+        return f"{dt}_k{m.group(2)}_c0_{'direct' if m.group(3) == '0' else 'transfer'}"
     m = re.search(r"native_kernel<(double|float), (\d), (\d), (\d)", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"

@@ -251,6 +251,46 @@ def test_step_kernels_give_bitwise_equal_results(ht, dtype):
             ht.set_tuning(k, v)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_pass_tuner_keeps_the_operator_and_the_results(ht, dtype):
+    """ht_tune_passes times identity passes on the operator: the represented
+    matrix is unchanged, every class gets a shape, and passes launched with
+    the tuned shapes give bitwise the results of the lane-patch kernel."""
+    rng = synth.make_rng(472)
+    n, m = 9, 3
+    H = synth.random_hermitian_dense(n, rng)
+    h = make(ht, n, m, H, dtype)
+    before = h.to_dense()
+    rows = h.tune_passes(1)
+    assert np.array_equal(h.to_dense(), before)
+    classes = {(r["k"], r["cross"], r["form"], r["low_intra"]) for r in rows}
+    # k = 1 and 2, 0-2 tile-selecting targets, both forms; m = 3 has no intra target at bit 3
+    assert (1, 0, "direct", True) in classes and (1, 1, "transfer", False) in classes
+    assert (2, 2, "direct", False) in classes and (2, 1, "transfer", True) in classes
+    assert all(r["ms"] > 0 and r["lane_ms"] > 0 for r in rows)
+    h.close()
+    ops = []
+    for _ in range(20):
+        k = int(rng.integers(1, 3))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        ops.append((t, synth.haar_unitary(1 << k, rng)[None] if rng.random() < 0.5
+                    else synth.random_kraus_set(k, 2, rng)))
+    out = []
+    for tune in ({}, {"stage": 0, "sync_waves": 0}):
+        for key, v in tune.items():
+            ht.set_tuning(key, v)
+        try:
+            g = make(ht, n, m, H, dtype)
+            for t, mats in ops:
+                g.apply_channel(t, mats)
+            out.append(g.raw_entries())
+            g.close()
+        finally:
+            for key in tune:
+                ht.set_tuning(key, -1)
+    assert np.array_equal(out[0], out[1])
+
+
 def test_native_gate_exactness(ht):
     """X twice is the identity bitwise; CNOT leaves the control-0 quarter
     bitwise unchanged; S leaves entries with equal target bits unchanged."""

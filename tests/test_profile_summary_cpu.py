@@ -14,6 +14,10 @@ def test_kernel_class():
         "ht::pair_kernel<1, 1, 0, 3, 2>": "c64_k1_c1_direct",
         "ht::pair_kernel<1, 0, 1, 0, 2>": "c64_k1_c0_transfer",
         "ht::pair_kernel<2, 2, 0, 3, 1>": "c64_k2_c2_direct",
+        "ht::conj_sync_kernel<double, 1, 1, 1, 3>": "c128_k1_c1_transfer",
+        "ht::conj_pipe_kernel<double, 2, 2, 0, 3, 512, true>": "c128_k2_c2_direct",
+        "ht::stage_kernel<double, 1, 0, 512, true>": "c128_k1_c0_direct",
+        "ht::stage_kernel<float, 2, 1, 256, false>": "c64_k2_c0_transfer",
         "ht::trace_partial_kernel<double>": None,
         "ht::batch_kernel<float>": None,
     }
