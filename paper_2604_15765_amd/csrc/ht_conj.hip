@@ -488,7 +488,16 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if constexpr (C == 0) {
     const uint64_t tile_bytes = (uint64_t)(2 * sizeof(T)) << (2 * g.m);
     int stage = tuning().stage;
-    if (stage < 0) stage = (big && !(K == 2 && FORM == 0 && low >= 3)) ? 1 : 0;
+    if (stage < 0) {
+      // operators of 1 GiB and more; complex64 too (its lane-patch and pair
+      // kernels ran 4.3-5.2 TB/s there, staged 5.0-5.75), except its k = 2
+      // transfer form, whose 16 x 16 matrix the staged pass reads far slower
+      const bool large = nent * 2 * sizeof(T) >= (1ull << 30);
+      stage = large && !(sizeof(T) == 8 && K == 2 && FORM == 0 && low >= 3) &&
+                      !(sizeof(T) == 4 && K == 2 && FORM == 1)
+                  ? 1
+                  : 0;
+    }
     if (shape >= 0) stage = (shape >= kShapeStage && shape <= kShapeStage58) ? 1 : 0;
     const int sth = tuning().stage_threads;
     const uint64_t step_bytes = 16ull * kStageVecs * (uint64_t)sth;

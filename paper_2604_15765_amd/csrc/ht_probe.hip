@@ -13,7 +13,15 @@
 //                    per lane: PAT 0 contiguous 1 KiB per instruction, PAT 1
 //                    the conjugation pass's 8 x 8 lane patch (8 rows of
 //                    128 B at a 512-byte stride per instruction);
-//   read_stream      read-only; write_stream  write-only; copy_stream  copy.
+//   read_stream      read-only; write_stream  write-only; copy_stream  copy;
+//   rmw_wg<NS,W,X>   workgroup bursts: W waves each move a 16 KiB chunk per
+//                    step, the chunks spread over NS far-apart regions; all
+//                    loads of a step complete (barrier) before any store; X:
+//                    through LDS (write, update the next wave's chunk, read
+//                    back) instead of in registers;
+//   xstage<NS>       512 threads move 128 KiB per step through LDS, as NS
+//                    runs in NS regions, with the next step's loads issued
+//                    before the current step is updated and stored.
 // Every kernel is a grid-stride loop over whole work items that lie inside
 // the buffer (items that would cross its end are not formed).
 #include <hip/hip_runtime.h>
@@ -115,6 +123,88 @@ __global__ void __launch_bounds__(256) copy_stream(u4* __restrict__ d, const u4*
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) d[i] = s[i];
 }
 
+template <int NS, int W, bool X>
+__global__ void __launch_bounds__(W * 64) rmw_wg(u4* __restrict__ p, uint64_t n16, unsigned salt) {
+  constexpr int WPR = W / NS;  // waves per region
+  __shared__ u4 lds[X ? W * 1024 : 1];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t r = w / WPR, sub = w % WPR;
+  const uint64_t slen = n16 / NS;
+  const uint64_t steps = slen / (1024 * WPR);
+  for (uint64_t it = blockIdx.x; it < steps; it += gridDim.x) {
+    u4* base = p + r * slen + (it * WPR + sub) * 1024;
+    u4 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(base + i * 64 + lane);
+    if constexpr (X) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[w * 1024 + i * 64 + lane] = v[i];
+      __syncthreads();
+      const uint32_t o = ((w + 1) % W) * 1024;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        u4 x = lds[o + i * 64 + lane];
+        x.x ^= salt;
+        x.w += salt;
+        lds[o + i * 64 + lane] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = lds[w * 1024 + i * 64 + lane];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        v[i].x ^= salt;
+        v[i].w += salt;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(v[i], base + i * 64 + lane);
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(512) xstage(u4* __restrict__ p, uint64_t n16, unsigned salt) {
+  constexpr int RUN = 8192 / NS;  // 16-byte words per run
+  __shared__ u4 lds[8192];
+  const uint32_t t = threadIdx.x;
+  const uint64_t slen = n16 / NS;
+  const uint64_t steps = slen / RUN;
+  auto addr = [&](uint64_t st, int j) -> uint64_t {
+    const uint32_t i = j * 512 + t;
+    return (uint64_t)(i / RUN) * slen + st * RUN + (i % RUN);
+  };
+  u4 v[16];
+  uint64_t st = blockIdx.x;
+  if (st < steps)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(p + addr(st, j));
+  for (; st < steps; st += gridDim.x) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds[j * 512 + t] = v[j];
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + gridDim.x < steps)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(p + addr(st + gridDim.x, j));
+    const uint32_t o = (t + 256) & 511;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      u4 x = lds[j * 512 + o];
+      x.x ^= salt;
+      x.w += salt;
+      lds[j * 512 + o] = x;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    u4 q[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) q[j] = lds[j * 512 + t];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) __builtin_nontemporal_store(q[j], p + addr(st, j));
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -147,6 +237,43 @@ int htp_tile(int pattern, void* buf, uint64_t ntiles, int grid, void* stream) {
     hipLaunchKernelGGL(tile_rmw<0>, dim3(grid), dim3(256), 0, s, p, ntiles, 7u);
   else if (pattern == 1)
     hipLaunchKernelGGL(tile_rmw<1>, dim3(grid), dim3(256), 0, s, p, ntiles, 7u);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
+// Workgroup bursts: ns regions (1, 4 or 16), waves per workgroup (4, 8, 16;
+// ns <= waves), xch: through LDS (4 or 8 waves).
+int htp_wg(int ns, int waves, int xch, void* buf, uint64_t n16, int grid, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  u4* p = reinterpret_cast<u4*>(buf);
+#define HTP_WG(NS, W, X)                                                                      \
+  if (ns == NS && waves == W && (xch != 0) == X) {                                            \
+    hipLaunchKernelGGL((rmw_wg<NS, W, X>), dim3(grid), dim3(W * 64), 0, s, p, n16, 7u);       \
+    return (int)hipGetLastError();                                                            \
+  }
+  HTP_WG(1, 4, false)
+  HTP_WG(1, 8, false)
+  HTP_WG(1, 16, false)
+  HTP_WG(1, 4, true)
+  HTP_WG(1, 8, true)
+  HTP_WG(4, 4, false)
+  HTP_WG(4, 16, false)
+  HTP_WG(16, 16, false)
+#undef HTP_WG
+  return (int)hipErrorInvalidValue;
+}
+
+// 128 KiB steps through LDS, prefetched: ns regions (1, 2 or 4).
+int htp_xstage(int ns, void* buf, uint64_t n16, int grid, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  u4* p = reinterpret_cast<u4*>(buf);
+  if (ns == 1)
+    hipLaunchKernelGGL(xstage<1>, dim3(grid), dim3(512), 0, s, p, n16, 7u);
+  else if (ns == 2)
+    hipLaunchKernelGGL(xstage<2>, dim3(grid), dim3(512), 0, s, p, n16, 7u);
+  else if (ns == 4)
+    hipLaunchKernelGGL(xstage<4>, dim3(grid), dim3(512), 0, s, p, n16, 7u);
   else
     return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();

@@ -43,8 +43,11 @@ def main():
     u64 = ctypes.c_uint64
 
     def best(fn, moved):
+        return best_of(fn, moved, grids)
+
+    def best_of(fn, moved, grid_list):
         res = 0.0
-        for g in grids:
+        for g in grid_list:
             assert fn(g) == 0
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -71,6 +74,20 @@ def main():
     for pat, name in ((0, "contiguous"), (1, "patch8x8")):
         r[f"tile_rmw_{name}_nt_GBps"] = best(
             lambda g, pat=pat: lib.htp_tile(pat, vp(a.data_ptr()), u64(ntiles), g, st), 2 * ntiles * 16384)
+    # workgroup bursts (reads of a step complete before its writes)
+    for ns, w, x in ((1, 4, 0), (1, 8, 0), (1, 16, 0), (1, 4, 1), (1, 8, 1), (4, 4, 0), (4, 16, 0), (16, 16, 0)):
+        wpr = w // ns
+        steps = (n16 // ns) // (1024 * wpr)
+        moved = 2 * 16 * ns * steps * wpr * 1024
+        name = f"wg_{ns}regions_{w}waves{'_lds' if x else ''}_GBps"
+        r[name] = best_of(lambda g, ns=ns, w=w, x=x: lib.htp_wg(ns, w, x, vp(a.data_ptr()), u64(n16), g, st),
+                          moved, (256, 192))
+    for ns in (1, 2, 4):
+        steps = (n16 // ns) // (8192 // ns)
+        moved = 2 * steps * 8192 * 16
+        for g in (256, 192):
+            r[f"xstage_{ns}regions_grid{g}_GBps"] = best_of(
+                lambda g_, ns=ns: lib.htp_xstage(ns, vp(a.data_ptr()), u64(n16), g_, st), moved, (g,))
     print(json.dumps(r), flush=True)
     if args.summary:
         write_summary(r, args.summary)
@@ -92,6 +109,11 @@ def write_summary(r: dict, path: str) -> None:
         "per load instruction,",
         "#   patch8x8 = the conjugation pass's lane patch (8 rows x 128 B at a 512-byte stride per "
         "instruction)",
+        "# wg_<S>regions_<W>waves: W waves of a workgroup move 16 KiB each per step from S far-apart regions, "
+        "all loads before any store (barrier);",
+        "#   _lds: through LDS; best of grids 256/192 workgroups",
+        "# xstage_<S>regions_grid<G>: 512 threads move 128 KiB per step through LDS in S runs, next step "
+        "prefetched; G workgroups",
         "",
     ]
     for k, v in r.items():
