@@ -538,7 +538,19 @@ const char* ht_kernel_class_name(int idx);
  * which a lane holds two blocks in adjacent columns and moves their entries
  * as 16-byte accesses; 0 off, 1 where it pays (every target tile-selecting,
  * or the intra target at bit 4 or above), 2 wherever it applies (no intra
- * target at bit 0, at least 4 free bits per tile dimension).  HT_EINVAL for an unknown name or value.  Set it
+ * target at bit 0, at least 4 free bits per tile dimension).  Further names
+ * select the launch shapes of the pass (every shape computes bitwise the
+ * same result; -1 = automatic where allowed): "stage" (-1, 0, 1) the
+ * LDS-staged intra-tile pass, "stage_threads" (256 or 512: 64 or 128 KiB
+ * steps), "stage_pipe" (0 or 1: prefetch the next step), "stage_grid" and
+ * "sync_grid" (0 = one workgroup per CU, else the number of workgroups),
+ * "stage_wg_per_cu" (1 or 2), "sync_waves" (-1, 0, 4, 8, 16: workgroup-wide
+ * steps for passes with a tile-selecting target), "sync_wg_per_cu",
+ * "sync_interleave" (-1, 0, 1), "pipe_waves" (0, 4, 8: steps with the next
+ * one prefetched), "pipe_barrier" (0 or 1), "pair_jp2" (0 or 1, default 1:
+ * complex64 pair passes with two tile-selecting targets in plain mode take
+ * two pairs per step).  A shape tuned by ht_tune_passes is used only while
+ * "stage" and "sync_waves" are -1 and "pipe_waves" is 0.  HT_EINVAL for an unknown name or value.  Set it
  * while no other thread enqueues work (a server's scheduler thread reads it). */
 ht_status ht_set_tuning(const char* name, int64_t value);
 

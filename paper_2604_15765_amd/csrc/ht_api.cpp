@@ -619,6 +619,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().native = (int)value;
     return HT_OK;
   }
+  if (k == "pair_jp2") {
+    if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "pair_jp2 must be 0 or 1");
+    ht::tuning().pair_jp2 = (int)value;
+    return HT_OK;
+  }
   if (k == "stage") {
     if (value < -1 || value > 1) return ht_fail(HT_EINVAL, "stage must be -1, 0 or 1");
     ht::tuning().stage = (int)value;

@@ -600,6 +600,17 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       }
       constexpr int JP = K == 1 ? 2 : 1;  // 16 entries per lane and step either way
       const dim3 grid((unsigned)wgs), block(threads);
+      if constexpr (K == 2 && KI == 0) {
+        // two pairs per step, the second the first's row-bit-3 neighbour,
+        // so that both halves of a mirrored tile's lines are read in one
+        // step (measured 3-4 % faster at (13, 14), (14, 15), (5, 15); the
+        // half-line stores still go out as separate instructions, so the
+        // counted write traffic stays about the same)
+        if (tuning().pair_jp2 == 1 && pmode == 0) {
+          hipLaunchKernelGGL((pair_kernel<K, C, FORM, 0, 2>), grid, block, 0, s, hp, g, cf, order);
+          return hipGetLastError();
+        }
+      }
       switch (pmode) {
         case 1: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 1, JP>), grid, block, 0, s, hp, g, cf, order); break;
         case 2: hipLaunchKernelGGL((pair_kernel<K, C, FORM, 2, JP>), grid, block, 0, s, hp, g, cf, order); break;

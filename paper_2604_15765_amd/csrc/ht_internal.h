@@ -31,6 +31,7 @@ struct LaunchTuning {
   int interleave = 1;       // patch order (lane_block): 0 runs, 1 alternating
   int pairs = 1;            // pair layout of complex64 passes (ht_pair.h): 0 off,
                             // 1 where it pays, 2 wherever it applies
+  int pair_jp2 = 1;         // complex64 two-cross pair passes in plain mode: two pairs per step
   int stage = -1;           // intra-tile passes staged through LDS in 64 KiB steps:
                             // -1 automatic, 0 off, 1 wherever the tile fits
   int stage_wg_per_cu = 1;  // workgroups per CU of the staged pass

@@ -189,13 +189,15 @@ STEP_TUNINGS = [
     {"sync_waves": 16},
     {"sync_waves": 8, "sync_interleave": 0},
     {"sync_waves": 4, "sync_interleave": 1},
+    # complex64 pair passes with two tile-selecting targets in plain mode: one pair per step
+    {"pair_jp2": 0},
     # steps with the next one prefetched, with and without the barrier
     {"pipe_waves": 4},
     {"pipe_waves": 4, "pipe_barrier": 0},
     {"pipe_waves": 8},
 ]
 STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
-                 "pipe_waves": 0, "pipe_barrier": 1, "native": 1}
+                 "pipe_waves": 0, "pipe_barrier": 1, "native": 1, "pair_jp2": 1}
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
