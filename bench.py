@@ -138,12 +138,16 @@ def cpu_baseline(n_full: int, seed: int) -> dict:
     }
 
 
-def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128) -> dict:
+def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128, h128) -> dict:
     """The same steps from the same initial state in complex64 storage (FP64
     arithmetic and reductions, the pair layout where it applies): its own
-    passes/s and HBM rate, and how far its readouts are from the complex128
-    run's after the same steps."""
+    passes/s and HBM rate; how far its readouts and 200,000 sampled entries
+    are from the complex128 run's after the same steps (the parity-tested
+    FP64 state); and both storage types against the CPU oracle after two
+    layers of the same mix at n = 11, with the complex64 bound."""
     import torch
+    import oracle
+    import synth
     h = ht.Herm(args.n, args.tile_log2, "c64")
     h.init_lowrank(G)
     h.scale(1.0 / h.trace())
@@ -171,6 +175,26 @@ def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128) -> dict:
     prof = h.profile_read()
     h.profile_enable(False)
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    rng = synth.make_rng(args.seed + 7)
+    rows = rng.integers(0, 1 << args.n, size=200000)
+    cols = rng.integers(0, 1 << args.n, size=200000)
+    e128 = h128.get_entries(rows, cols)
+    e64 = h.get_entries(rows, cols)
+    passes = nops + sum(len(layers[l]) for l in range(args.warmup))
+    # both storage types against the oracle on the same mix at n = 11
+    n11 = 11
+    r11 = synth.make_rng(args.seed + 11)
+    G11 = synth.ginibre_factor(n11, 16, r11)
+    ops11 = synth.layer_n16(0, r11, n=n11) + synth.layer_n16(1, r11, n=n11)
+    ref11 = oracle.apply_ops_local(oracle.density_from_factor(G11), ops11)
+    err11 = {}
+    for dt in ("c128", "c64"):
+        g = ht.Herm(n11, args.tile_log2, dt).init_lowrank(G11)
+        g.scale(1.0 / g.trace())
+        for op in ops11:
+            g.apply_op(op)
+        err11[dt] = float(np.linalg.norm(g.to_dense() - ref11) / np.linalg.norm(ref11))
+        g.close()
     out = {
         "value": nops / elapsed,
         "unit": "gate-conj/s",
@@ -181,6 +205,12 @@ def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128) -> dict:
         "dominant_GBps": dom["bytes"] / (dom["ms"] * 1e-3) / 1e9,
         "trace_diff_vs_c128": abs(tr - tr_c128),
         "pauli_expectation_diff_vs_c128": abs(ev - ev_c128),
+        "sampled_rel_frobenius_vs_c128": float(np.linalg.norm(e64 - e128) / np.linalg.norm(e128)),
+        "sampled_entries": int(rows.size),
+        "passes": passes,
+        "bound_rel_frobenius": (passes + 1) * 2.0 ** -24,
+        "n11_vs_oracle": {"passes": len(ops11), "rel_frobenius": err11,
+                          "bound_c64": (len(ops11) + 1) * 2.0 ** -24, "tolerance_c128": 1e-12},
     }
     h.close()
     log(f"[bench] complex64: {out['value']:.1f} gate-conj/s, {out['hbm_GBps']:.0f} GB/s")
@@ -597,7 +627,7 @@ def main():
         "final_pauli_expectation": ev,
     }
     if args.dtype == "c128" and not args.no_c64:
-        out["complex64"] = c64_run(ht, G, layers, args, codes, coeffs, tr, ev)
+        out["complex64"] = c64_run(ht, G, layers, args, codes, coeffs, tr, ev, h)
     if not args.no_fused:
         out["fused"] = fused_run(ht, h, G, layers, args, codes, coeffs, tr, ev)
     if not args.no_serve or not args.no_batched:

@@ -427,6 +427,8 @@ def run_paper(args):
         else:
             h = ht.Herm(n, 5).init_lowrank(torch.from_numpy(synth.ginibre_factor(n, 4, rng)).to("cuda"))
             h.scale(1.0 / h.trace())
+        if n >= 12 and not args.no_tune:
+            h.tune_passes(2)  # launch shapes per pass class (identity passes: the operator is unchanged)
         stream = h.stream
         U1 = synth.haar_unitary(2, rng)
         U2 = synth.haar_unitary(4, rng)
@@ -489,6 +491,8 @@ def run_paper(args):
     G, ops, (codes, coeffs) = synth.circuit_sweep(n=14)
     h = ht.Herm(14, 5).init_lowrank(torch.from_numpy(G).to("cuda"))
     h.scale(1.0 / h.trace())
+    if not args.no_tune:
+        h.tune_passes(2)
     h.profile_reset()
     h.profile_enable(True)
     torch.cuda.synchronize()
@@ -642,6 +646,7 @@ def main():
     q.add_argument("--seed", type=int, default=530)
     q.add_argument("--ns", default="6,8,10,12,14,16")
     q.add_argument("--reps", type=int, default=10, help="timing intervals per (n, op, position)")
+    q.add_argument("--no-tune", action="store_true", help="skip the pass tuner (ht_tune_passes) for n >= 12")
     q.add_argument("--no-n14-oracle", dest="n14_oracle", action="store_false",
                    help="skip the whole-state oracle run of the n = 14 sweep circuit (minutes on the host)")
     args = p.parse_args()

@@ -222,3 +222,33 @@ def test_ctypes_structs_match_the_header(ht, pyname, cname, tmp_path):
     size, offsets = _c_layout(cname, fields, tmp_path)
     assert ctypes.sizeof(cls) == size
     assert [getattr(cls, f).offset for f in fields] == offsets
+
+
+def test_pass_shape_arguments(ht):
+    """ht_set_pass_shape (no GPU work): classes an operator shape can have
+    and shapes that apply to them are accepted, everything else returns
+    HT_EINVAL; shape -1 hands a class back to the automatic choice."""
+    f = ht.lib.ht_set_pass_shape
+    C128, C64 = 0, 1
+    # dtype, n, tile_log2, k, cross, form, low, shape
+    ok = [(C128, 16, 5, 1, 0, 0, 1, 1), (C128, 16, 5, 1, 1, 1, 0, 5), (C64, 16, 5, 2, 2, 0, 0, 6),
+          (C128, 16, 5, 2, 1, 0, 1, 0), (C128, 16, 5, 1, 0, 0, 0, -1), (C64, 9, 3, 2, 0, 1, 1, 3)]
+    bad = [(2, 16, 5, 1, 0, 0, 0, 0),    # unknown dtype
+           (C128, 0, 5, 1, 0, 0, 0, 0),  # n out of range
+           (C128, 16, 9, 1, 0, 0, 0, 0),  # tile_log2 out of range
+           (C128, 16, 5, 3, 0, 0, 0, 0),  # k = 3 has no tuned shapes
+           (C128, 16, 5, 1, 2, 0, 0, 0),  # more tile-selecting targets than targets
+           (C128, 5, 5, 1, 1, 0, 0, 0),   # one tile: no tile-selecting target
+           (C128, 16, 5, 1, 1, 0, 1, 0),  # no intra target, yet "low"
+           (C128, 16, 5, 1, 0, 2, 0, 0),  # form
+           (C128, 16, 5, 1, 1, 0, 0, 1),  # staged shape with a tile-selecting target
+           (C128, 16, 5, 1, 0, 0, 0, 4),  # step shape without one
+           (C128, 16, 5, 1, 0, 0, 0, 7)]  # unknown shape
+    try:
+        for args in ok:
+            assert f(*args) == 0, (args, ht.lib.ht_last_error())
+        for args in bad:
+            assert f(*args) == 1, args
+    finally:
+        for args in ok:
+            f(*args[:7], -1)
