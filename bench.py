@@ -602,7 +602,8 @@ def main():
                          f"Haar U(4), amplitude damping 0.01 on all qubits) + trace + 64-term Pauli sum"),
             "n": n, "tile_edge": 1 << h.tile_log2, "storage": args.dtype,
             "ops_per_step": nops / args.steps, "storage_bytes": h.nbytes, "tuning": tuning,
-            "tuned_shapes": {f"k{r['k']}_c{r['cross']}_{r['form']}{'_low' if r['low_intra'] else ''}": r["shape"]
+            "tuned_shapes": {f"k{r['k']}_c{r['cross']}_{r['form']}{'_low' if r['low_intra'] else ''}"
+                             f"{'_far' if r.get('far') else ''}": r["shape"]
                              for r in tuned},
             "tune_s": tune_s,
         },

@@ -546,7 +546,9 @@ const char* ht_kernel_class_name(int idx);
  * "sync_grid" (0 = one workgroup per CU, else the number of workgroups),
  * "stage_wg_per_cu" (1 or 2), "sync_waves" (-1, 0, 4, 8, 16: workgroup-wide
  * steps for passes with a tile-selecting target), "sync_wg_per_cu",
- * "sync_interleave" (-1, 0, 1), "pipe_waves" (0, 4, 8: steps with the next
+ * "sync_interleave" (-1, 0, 1), "sync_order" (-1 automatic; 0 a workgroup
+ * step takes whole groups, 1 one quarter of every tile of consecutive
+ * groups, 2 the same of every other group), "pipe_waves" (0, 4, 8: steps with the next
  * one prefetched), "pipe_barrier" (0 or 1), "pair_jp2" (0 or 1, default 1:
  * complex64 pair passes with two tile-selecting targets in plain mode take
  * two pairs per step).  A shape tuned by ht_tune_passes is used only while
@@ -559,10 +561,11 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  * launch shape streams fastest differs by a few percent between devices.
  * For every pass class of h's shape (storage type, n, tile edge) -- k = 1
  * and 2 targets, 0 to 2 of them tile-selecting, direct and transfer form,
- * an intra target below bit 3 or not -- this times each candidate shape
- * (the lane-patch kernel; the LDS-staged intra-tile pass or 16-wave
- * workgroup steps at grids of 1, 3/4 and 5/8 workgroups per CU) on identity
- * passes of h, reps timed rounds after one warm-up round, and keeps the
+ * an intra target below bit 3 or not, the highest tile-selecting target
+ * below tile bit 4 or not -- this times each candidate shape (the
+ * lane-patch kernel; the LDS-staged intra-tile pass or 16-wave workgroup
+ * steps in three item orders, each at grids of 1, 3/4 and 5/8 workgroups
+ * per CU) on identity passes of h, reps timed rounds after one warm-up round, and keeps the
  * fastest for operators of that shape.  The choice is process-wide and is
  * used while the launch tuning (ht_set_tuning "stage", "sync_waves",
  * "pipe_waves") is automatic; every shape computes bitwise the same result.
@@ -570,11 +573,14 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  * negative zero may become a positive one, and the stored upper halves of
  * diagonal tiles are rewritten as the conjugates of the lower ones, which
  * is the same matrix).  Synchronises h's stream; at n = 16 it takes about
- * 3 s.  rows (host, may be NULL when max_rows = 0): up to max_rows records
- * of 7 doubles per class: k, tile-selecting targets, form (0 direct, 1
- * transfer), low (1: an intra target below bit 3), chosen shape (0 lane
+ * 10 s.  rows (host, may be NULL when max_rows = 0): up to max_rows records
+ * of 8 doubles per class: k, tile-selecting targets, form (0 direct, 1
+ * transfer), low (1: an intra target below bit 3), far (1: the highest
+ * tile-selecting target at tile bit 4 or above), chosen shape (0 lane
  * patch, 1-3 staged at 1, 3/4, 5/8 workgroups per CU, 4-6 workgroup steps
- * at the same grids), its ms per pass, the lane-patch kernel's ms per pass;
+ * of whole groups at the same grids, 7-9 steps of one quarter of every tile
+ * of 16 groups, 10-12 the same of every other group of 32), its ms per
+ * pass, the lane-patch kernel's ms per pass;
  * nrows (may be NULL): classes tuned.  HT_EINVAL for a NULL handle, reps
  * outside [1, 16] or rows NULL with max_rows > 0.  Call it while no other
  * thread enqueues passes (it switches the process-wide launch tuning). */
@@ -582,11 +588,13 @@ ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* rows, int* 
 
 /* Set the launch shape of one pass class on operators of the given storage
  * type, n and tile edge, as ht_tune_passes would (for example from the
- * records of an earlier ht_tune_passes run; k, cross, form, low and shape as
- * in those records); shape -1 returns the class to the automatic choice.  No
- * GPU work.  HT_EINVAL for a class the operator shape cannot have, a staged
- * shape with a tile-selecting target or a step shape without one. */
-ht_status ht_set_pass_shape(int dtype, int n, int tile_log2, int k, int cross, int form, int low, int shape);
+ * records of an earlier ht_tune_passes run; k, cross, form, low, far and
+ * shape as in those records); shape -1 returns the class to the automatic
+ * choice.  No GPU work.  HT_EINVAL for a class the operator shape cannot
+ * have, a staged shape with a tile-selecting target or a step shape without
+ * one. */
+ht_status ht_set_pass_shape(int dtype, int n, int tile_log2, int k, int cross, int form, int low, int far,
+                            int shape);
 
 /* Pure host function (no GPU): the per-op preparation the library performs
  * before a launch, exposed for testing.  Given the same arguments as

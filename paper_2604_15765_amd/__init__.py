@@ -90,7 +90,7 @@ def _load():
         "ht_prepare_op": (c_int, [c_int, c_int, c_int, vp, c_int, vp, c_int, vp, P(c_int), P(c_int), vp]),
         "ht_set_tuning": (c_int, [ctypes.c_char_p, c_int64]),
         "ht_tune_passes": (c_int, [vp, c_int, c_int, vp, P(c_int)]),
-        "ht_set_pass_shape": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+        "ht_set_pass_shape": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "ht_batch_create": (c_int, [P(vp)]),
         "ht_batch_destroy": (c_int, [vp]),
         "ht_batch_set_param": (c_int, [vp, ctypes.c_char_p, c_int64]),
@@ -221,7 +221,9 @@ def set_tuning(name: str, value: int) -> None:
     _check(lib.ht_set_tuning(name.encode(), int(value)))
 
 
-PASS_SHAPES = ("lane", "stage", "stage_3/4", "stage_5/8", "steps", "steps_3/4", "steps_5/8")
+PASS_SHAPES = ("lane", "stage", "stage_3/4", "stage_5/8", "steps", "steps_3/4", "steps_5/8",
+               "steps_quarter", "steps_quarter_3/4", "steps_quarter_5/8",
+               "steps_quarter_alt", "steps_quarter_alt_3/4", "steps_quarter_alt_5/8")
 
 
 def set_pass_shape(dtype: str, n: int, tile_log2: int, row: dict) -> None:
@@ -229,7 +231,8 @@ def set_pass_shape(dtype: str, n: int, tile_log2: int, row: dict) -> None:
     None: back to the automatic choice)."""
     shape = -1 if row.get("shape") is None else PASS_SHAPES.index(row["shape"])
     _check(lib.ht_set_pass_shape(_DTYPES[dtype], int(n), int(tile_log2), int(row["k"]), int(row["cross"]),
-                                 1 if row["form"] == "transfer" else 0, 1 if row["low_intra"] else 0, shape))
+                                 1 if row["form"] == "transfer" else 0, 1 if row["low_intra"] else 0,
+                                 1 if row.get("far") else 0, shape))
 
 
 def prepare_op(n: int, tile_log2: int, targets: Sequence[int], mats, picture: int = SCHRODINGER):
@@ -451,11 +454,11 @@ class Herm:
         """ht_tune_passes: time the launch shapes of every pass class on this
         operator (identity passes: the represented matrix is unchanged) and
         keep the fastest; returns one dict per class."""
-        rows = np.zeros((64, 7), dtype=np.float64)
+        rows = np.zeros((64, 8), dtype=np.float64)
         nr = ctypes.c_int()
         _check(lib.ht_tune_passes(self._h, int(reps), 64, _ptr(rows), ctypes.byref(nr)))
         return [dict(k=int(r[0]), cross=int(r[1]), form="transfer" if r[2] else "direct", low_intra=bool(r[3]),
-                     shape=PASS_SHAPES[int(r[4])], ms=float(r[5]), lane_ms=float(r[6]))
+                     far=bool(r[4]), shape=PASS_SHAPES[int(r[5])], ms=float(r[6]), lane_ms=float(r[7]))
                 for r in rows[:min(nr.value, 64)]]
 
     def scale(self, alpha: float) -> None:

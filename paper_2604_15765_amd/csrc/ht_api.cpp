@@ -665,6 +665,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     ht::tuning().sync_interleave = (int)value;
     return HT_OK;
   }
+  if (k == "sync_order") {
+    if (value < -1 || value > 2) return ht_fail(HT_EINVAL, "sync_order must be -1, 0, 1 or 2");
+    ht::tuning().sync_order = (int)value;
+    return HT_OK;
+  }
   if (k == "pipe_barrier") {
     if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "pipe_barrier must be 0 or 1");
     ht::tuning().pipe_barrier = (int)value;

@@ -60,18 +60,21 @@ __global__ void __launch_bounds__(256)
 // ------------------------------------------------------- workgroup-wide steps
 
 // The pass with its steps taken by a whole workgroup at once: the waves of a
-// workgroup take consecutive (group, step) items -- whole groups of
-// neighbouring tiles when a workgroup has as many waves as a group has steps
-// -- load all their blocks, meet at a barrier, then compute and store.  Every
-// tile run that the workgroup covers in one step is then read completely
-// before any of it is written back (measured on MI355X: in-place streams run
-// faster in long read and write bursts than when each wave alternates on its
-// own).  Same lanes, same block arithmetic as conj_kernel: bitwise the same
-// results.
+// workgroup take (group, step) items (sync_item: whole groups of
+// neighbouring tiles, or one quarter of the tiles of many groups), load all
+// their blocks, meet at a barrier, then compute and store.  Every tile run
+// that the workgroup covers in one step is then read completely before any
+// of it is written back (measured on MI355X: in-place streams run faster in
+// long read and write bursts than when each wave alternates on its own).
+// The quarter orders keep the address bits just above a 4 KiB run equal
+// across a workgroup step; an operator-sized probe measured in-place streams
+// at 6.0-6.3 TB/s when every workgroup step's 4 KiB runs shared address
+// bits 12-14, against 5.3-5.6 for contiguous 64 KiB runs.  Same lanes, same
+// block arithmetic as conj_kernel: bitwise the same results.
 template <typename T, int K, int C, int FORM, int MODE>
 __global__ void __launch_bounds__(1024)
     conj_sync_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
-                     const double* __restrict__ coef) {
+                     const double* __restrict__ coef, int r, int par) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wpb = blockDim.x >> 6;
@@ -82,15 +85,17 @@ __global__ void __launch_bounds__(1024)
   constexpr int D = 1 << K;
   const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
   const int sl = 31 - __builtin_clz(steps);
-  const uint64_t items = g.ngroups << sl;
+  const uint64_t nu = sync_units(g.ngroups, sl, wpb, r, par);
   const uint32_t nblk = 1u << (2 * g.F);
   // the loop bound is the same for every wave of the workgroup (barrier)
-  for (uint64_t base = (uint64_t)blockIdx.x * wpb; base < items; base += (uint64_t)gridDim.x * wpb) {
-    const uint64_t it = base + wib;
-    const bool valid = it < items;
+  for (uint64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    uint64_t grp;
+    uint32_t step;
+    sync_item(u, wib, wpb, sl, r, par, grp, step);
+    const bool valid = grp < g.ngroups;
     GroupCtx<C> gc;
-    group_ctx<K, C>(valid ? (it >> sl) : 0, g, gc);
-    const uint32_t j0 = (uint32_t)(it & (steps - 1)) * JU;
+    group_ctx<K, C>(valid ? grp : 0, g, gc);
+    const uint32_t j0 = step * JU;
     BlockPos bp[JU];
     typename Mem::R x[JU][D * D];
 #pragma unroll
@@ -480,11 +485,13 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   // tile-selecting one stays on the lane-patch kernel (slower in steps).
   constexpr int KI = K - C;
   const int low = KI > 0 ? g.ipos[0] : 99;
+  // highest tile-selecting target at tile bit 4 or above
+  const int far = (C > 0 && g.cpos[C > 0 ? C - 1 : 0] >= 4) ? 1 : 0;
   // a shape the pass tuner picked for this class and operator shape, used
   // while the launch tuning is automatic
   int shape = -1;
   if (tuning().stage < 0 && tuning().sync_waves < 0 && tuning().pipe_waves == 0)
-    shape = tuned_shape(sizeof(T) == 8 ? 0 : 1, n, g.m, K, C, FORM, low < 3 ? 1 : 0);
+    shape = tuned_shape(sizeof(T) == 8 ? 0 : 1, n, g.m, K, C, FORM, low < 3 ? 1 : 0, far);
   if constexpr (C == 0) {
     const uint64_t tile_bytes = (uint64_t)(2 * sizeof(T)) << (2 * g.m);
     int stage = tuning().stage;
@@ -498,7 +505,7 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
                   ? 1
                   : 0;
     }
-    if (shape >= 0) stage = (shape >= kShapeStage && shape <= kShapeStage58) ? 1 : 0;
+    if (shape >= 0) stage = shape_is_stage(shape) ? 1 : 0;
     const int sth = tuning().stage_threads;
     const uint64_t step_bytes = 16ull * kStageVecs * (uint64_t)sth;
     if (stage == 1 && tile_bytes <= step_bytes) {
@@ -549,25 +556,44 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
     // workgroup-wide steps
     int sw = tuning().sync_waves;
     if (sw < 0) sw = (big && C > 0 && low >= 3 && !(K == 2 && C == 1)) ? 16 : 0;
-    if (shape >= 0) sw = (C > 0 && shape >= kShapeSync && shape <= kShapeSync58) ? 16 : 0;
+    if (shape >= 0) sw = (C > 0 && shape_is_sync(shape)) ? 16 : 0;
     if (sw > 0) {
       ConjGeom<K, C> gs = g;
+      // Item order.  Measured at n = 16, c128 (TB/s of algorithmic traffic,
+      // whole groups -> quarters -> quarters of every other group): k = 1
+      // at tile bit 0 5.46 -> 5.67 -> 5.58, bit 3 5.32 -> 5.45 -> 5.38,
+      // bit 5 5.33 -> 5.43 -> 5.65, bit 8 5.28 -> 5.50 -> 5.87, bit 10
+      // 5.23 -> 5.20 -> 5.40; two tile-selecting targets at bits (0, 1)
+      // 5.30 -> 5.44 (quarters), (4, 5) 5.26 -> 5.20, (9, 10) 5.08 -> 4.90.
+      int ord = tuning().sync_order;
+      if (shape >= 0) ord = shape_sync_order(shape);
+      if (ord < 0) ord = (K == 1 && C == 1) ? (far ? 2 : 1) : (K == 2 && C == 2 && !far) ? 1 : 0;
       int ilv = tuning().sync_interleave;
-      if (ilv < 0) ilv = C == 2 ? 0 : (use_interleave((int)sizeof(T) * 2) ? 1 : 0);
+      // quarters need the row-run patch order (a step's patches then cover
+      // whole rows of the tile)
+      if (ilv < 0) ilv = (ord != 0 || C == 2) ? 0 : (use_interleave((int)sizeof(T) * 2) ? 1 : 0);
       gs.ilv = ilv != 0;
-      const uint64_t wpb = (uint64_t)sw;
-      const uint64_t items = g.ngroups * steps;
-      uint64_t wg = (items + wpb - 1) / wpb;
+      const int sl = 31 - __builtin_clz((uint32_t)steps);
+      const int lw = 31 - __builtin_clz((uint32_t)sw);
+      const int rmax = sl < lw ? sl : lw;
+      // steps that share the patches' row bits: 2^(F - s) patches of 64
+      // blocks, conj_unroll of them per step
+      constexpr int JU = conj_unroll(K, (int)sizeof(T) * 2);
+      int r = g.F - g.s - (JU == 4 ? 2 : JU == 2 ? 1 : 0);
+      if (ord == 0 || r > rmax) r = rmax;
+      if (r < 0) r = 0;
+      const int par = ord == 2 ? 1 : 0;
+      uint64_t wg = sync_units(g.ngroups, sl, (uint32_t)sw, r, par);
       uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
                                              : (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
       if (shape >= 0) wcap = shape_grid(shape, num_cu);
       if (wg > wcap) wg = wcap;
       const dim3 grid((unsigned)wg), block((unsigned)(64 * sw));
       switch (smode) {
-        case 1: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 1>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
-        case 2: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 2>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
-        case 3: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 3>), grid, block, 0, s, hp, gs, cf, coef_dev); break;
-        default: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 0>), grid, block, 0, s, hp, gs, cf, coef_dev);
+        case 1: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 1>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
+        case 2: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 2>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
+        case 3: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 3>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
+        default: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 0>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par);
       }
       return hipGetLastError();
     }

@@ -255,4 +255,17 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   return 0;
 }
 
+// The item order of the workgroup-wide step kernel: for every unit
+// u < sync_units(...) and wave w < wpb, grp[u * wpb + w] and step[...] as
+// sync_item gives them.  Returns the number of units, or 0 when they exceed
+// max_units.
+uint64_t htc_sync_items(uint64_t ngroups, int sl, uint32_t wpb, int r, int par, uint64_t max_units,
+                        uint64_t* grp, uint32_t* step) {
+  const uint64_t nu = ht::sync_units(ngroups, sl, wpb, r, par);
+  if (nu > max_units) return 0;
+  for (uint64_t u = 0; u < nu; ++u)
+    for (uint32_t w = 0; w < wpb; ++w) ht::sync_item(u, w, wpb, sl, r, par, grp[u * wpb + w], step[u * wpb + w]);
+  return nu;
+}
+
 }  // extern "C"

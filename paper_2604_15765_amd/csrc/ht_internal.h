@@ -42,6 +42,9 @@ struct LaunchTuning {
   int sync_waves = -1;      // passes with a tile-selecting target in workgroup-wide
                             // steps: -1 automatic, 0 off, else waves per workgroup (4, 8, 16)
   int sync_wg_per_cu = 1;   // workgroups per CU of the synchronised pass
+  int sync_order = -1;      // items of a synchronised workgroup step: -1 automatic, 0 whole
+                            // groups, 1 one quarter of every tile of consecutive groups,
+                            // 2 the same of every other group
   int sync_interleave = -1; // patch order of the synchronised pass: -1 automatic (0 for two
                             // tile-selecting targets, else as "interleave"), 0 or 1
   int pipe_waves = 0;       // steps with the next one prefetched: 0 off, 4 or 8 waves per workgroup
@@ -51,27 +54,34 @@ LaunchTuning& tuning();
 
 // Launch shapes of the conjugation pass that the pass tuner (ht_tune_passes)
 // chooses between for a class of passes.  Every shape computes the same
-// blocks with the same arithmetic (bitwise equal results).
+// blocks with the same arithmetic (bitwise equal results).  The grids are
+// 1, 3/4 and 5/8 workgroups per CU; the 16-wave workgroup steps come in
+// three item orders (conj_sync_kernel): whole groups, one quarter of every
+// tile of 16 consecutive groups, and one quarter of every other group.
 enum PassShape {
   kShapeLane = 0,      // lane-patch kernel (conj_kernel), automatic grid
-  kShapeStage = 1,     // LDS-staged intra-tile pass, grid: one workgroup per CU
-  kShapeStage34 = 2,   //   ... three workgroups per four CUs
-  kShapeStage58 = 3,   //   ... five per eight
-  kShapeSync = 4,      // 16-wave workgroup-wide steps, one workgroup per CU
-  kShapeSync34 = 5,
-  kShapeSync58 = 6,
-  kShapeCount = 7
+  kShapeStage = 1,     // LDS-staged intra-tile pass, 3 grids (1..3)
+  kShapeSync = 4,      // 16-wave workgroup steps, whole groups (4..6)
+  kShapeSyncQ = 7,     //   ... quarters of consecutive groups (7..9)
+  kShapeSyncQA = 10,   //   ... quarters of every other group (10..12)
+  kShapeCount = 13
 };
+inline bool shape_is_stage(int shape) { return shape >= kShapeStage && shape < kShapeSync; }
+inline bool shape_is_sync(int shape) { return shape >= kShapeSync && shape < kShapeCount; }
+// Item order of a step shape: 0 whole groups, 1 quarters, 2 quarters of every other group.
+inline int shape_sync_order(int shape) { return (shape - kShapeSync) / 3; }
 // Grid of a shape: workgroups for num_cu compute units.
 inline uint64_t shape_grid(int shape, int num_cu) {
-  const int f = (shape == kShapeStage34 || shape == kShapeSync34) ? 6 : (shape == kShapeStage58 || shape == kShapeSync58) ? 5 : 8;
+  const int i = shape_is_stage(shape) ? shape - kShapeStage : shape_is_sync(shape) ? (shape - kShapeSync) % 3 : 0;
+  const int f = i == 1 ? 6 : i == 2 ? 5 : 8;
   return (uint64_t)num_cu * (uint64_t)f / 8u;
 }
 // The tuned shape of a pass class on operators of this storage type and
 // shape (n, effective tile exponent m); low: an intra target lies below
-// bit 3.  -1 when none has been tuned.
-int tuned_shape(int dtype, int n, int m, int k, int c, int form, int low);
-void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int shape);
+// bit 3; far: the highest tile-selecting target is tile bit 4 or above.
+// -1 when none has been tuned.
+int tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int far);
+void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int far, int shape);
 
 // Workgroups per CU for a kernel family: the tuning value if set, else the
 // family's measured default auto_value.

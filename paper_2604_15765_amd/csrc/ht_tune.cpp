@@ -24,7 +24,7 @@
 namespace {
 
 struct ShapeEntry {
-  int dtype, n, m, k, c, form, low, shape;
+  int dtype, n, m, k, c, form, low, far, shape;
 };
 
 std::mutex g_mu;
@@ -34,22 +34,24 @@ std::vector<ShapeEntry> g_shapes;
 
 namespace ht {
 
-int tuned_shape(int dtype, int n, int m, int k, int c, int form, int low) {
+int tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int far) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (const auto& e : g_shapes)
-    if (e.dtype == dtype && e.n == n && e.m == m && e.k == k && e.c == c && e.form == form && e.low == low)
+    if (e.dtype == dtype && e.n == n && e.m == m && e.k == k && e.c == c && e.form == form && e.low == low &&
+        e.far == far)
       return e.shape;
   return -1;
 }
 
-void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int shape) {
+void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, int far, int shape) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& e : g_shapes)
-    if (e.dtype == dtype && e.n == n && e.m == m && e.k == k && e.c == c && e.form == form && e.low == low) {
+    if (e.dtype == dtype && e.n == n && e.m == m && e.k == k && e.c == c && e.form == form && e.low == low &&
+        e.far == far) {
       e.shape = shape;
       return;
     }
-  g_shapes.push_back(ShapeEntry{dtype, n, m, k, c, form, low, shape});
+  g_shapes.push_back(ShapeEntry{dtype, n, m, k, c, form, low, far, shape});
 }
 
 }  // namespace ht
@@ -57,33 +59,45 @@ void set_tuned_shape(int dtype, int n, int m, int k, int c, int form, int low, i
 namespace {
 
 // One pass class: k targets of which c select tiles, the form, whether an
-// intra target lies below bit 3, and the target sets timed for it.
+// intra target lies below bit 3, whether the highest tile-selecting target
+// is tile bit 4 or above (far), and the target sets timed for it.
 struct TuneClass {
-  int k, c, form, low;
+  int k, c, form, low, far;
   std::vector<std::vector<int>> targets;
 };
 
 std::vector<TuneClass> tune_classes(int n, int m) {
   std::vector<TuneClass> out;
   const int cross = n - m;  // tile-selecting qubits
+  const bool has_far = cross >= 5;
   for (int form = 0; form < 2; ++form) {
     // intra-tile: low targets, and targets at bit 3 and above where the tile has them
-    if (m >= 1) out.push_back({1, 0, form, 1, {{0}}});
-    if (m >= 4) out.push_back({1, 0, form, 0, {{m - 1}}});
-    if (m >= 2) out.push_back({2, 0, form, 1, {{0, 1}}});
-    if (m >= 5) out.push_back({2, 0, form, 0, {{m - 2, m - 1}}});
-    // one tile-selecting target: the lowest and the highest tile bit
+    if (m >= 1) out.push_back({1, 0, form, 1, 0, {{0}}});
+    if (m >= 4) out.push_back({1, 0, form, 0, 0, {{m - 1}}});
+    if (m >= 2) out.push_back({2, 0, form, 1, 0, {{0, 1}}});
+    if (m >= 5) out.push_back({2, 0, form, 0, 0, {{m - 2, m - 1}}});
+    // one tile-selecting target: tile bits below 4 and from 4 up
     if (cross >= 1) {
       std::vector<std::vector<int>> t1 = {{m}};
-      if (n - 1 != m) t1.push_back({n - 1});
-      out.push_back({1, 1, form, 0, t1});
-      if (m >= 1) out.push_back({2, 1, form, 1, {{0, n - 1}}});
-      if (m >= 4) out.push_back({2, 1, form, 0, {{m - 1, n - 1}}});
+      if (cross >= 3) t1.push_back({m + 2});
+      out.push_back({1, 1, form, 0, 0, t1});
+      if (has_far) {
+        std::vector<std::vector<int>> tf = {{n - 1}};
+        if (m + 5 < n - 1) tf.push_back({m + 5});
+        out.push_back({1, 1, form, 0, 1, tf});
+      }
+      if (m >= 1) {
+        out.push_back({2, 1, form, 1, 0, {{0, m}}});
+        if (has_far) out.push_back({2, 1, form, 1, 1, {{0, n - 1}}});
+      }
+      if (m >= 4) {
+        out.push_back({2, 1, form, 0, 0, {{m - 1, m}}});
+        if (has_far) out.push_back({2, 1, form, 0, 1, {{m - 1, n - 1}}});
+      }
     }
     if (cross >= 2) {
-      std::vector<std::vector<int>> t2 = {{m, m + 1}};
-      if (n - 2 != m) t2.push_back({n - 2, n - 1});
-      out.push_back({2, 2, form, 0, t2});
+      out.push_back({2, 2, form, 0, 0, {{m, m + 1}}});
+      if (has_far) out.push_back({2, 2, form, 0, 1, {{n - 2, n - 1}}});
     }
   }
   return out;
@@ -135,17 +149,20 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
     const bool skip_stage = h->dtype == HT_C64 && tc.k == 2 && tc.form == 1;  // measured 7x slower staged
     std::vector<int> cands = {ht::kShapeLane};
     if (tc.c == 0 && !skip_stage)
-      cands.insert(cands.end(), {ht::kShapeStage, ht::kShapeStage34, ht::kShapeStage58});
-    if (tc.c > 0) cands.insert(cands.end(), {ht::kShapeSync, ht::kShapeSync34, ht::kShapeSync58});
+      for (int sh = ht::kShapeStage; sh < ht::kShapeSync; ++sh) cands.push_back(sh);
+    if (tc.c > 0)
+      for (int sh = ht::kShapeSync; sh < ht::kShapeCount; ++sh) cands.push_back(sh);
     double best = 1e300, lane_ms = 0.0;
     int best_shape = ht::kShapeLane;
     for (int shape : cands) {
       ht::tuning() = saved;
       ht::tuning().pipe_waves = 0;
-      ht::tuning().stage = (shape >= ht::kShapeStage && shape <= ht::kShapeStage58) ? 1 : 0;
+      ht::tuning().stage = ht::shape_is_stage(shape) ? 1 : 0;
       ht::tuning().stage_grid = ht::tuning().stage ? (int)ht::shape_grid(shape, h->num_cu) : 0;
-      ht::tuning().sync_waves = (shape >= ht::kShapeSync && shape <= ht::kShapeSync58) ? 16 : 0;
+      ht::tuning().sync_waves = ht::shape_is_sync(shape) ? 16 : 0;
       ht::tuning().sync_grid = ht::tuning().sync_waves ? (int)ht::shape_grid(shape, h->num_cu) : 0;
+      ht::tuning().sync_order = ht::tuning().sync_waves ? ht::shape_sync_order(shape) : -1;
+      ht::tuning().sync_interleave = -1;
       double tmin = 1e300;
       for (int r = 0; r <= reps && st == HT_OK; ++r) {  // the first round warms up
         double t = 0.0;
@@ -179,16 +196,17 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
       }
     }
     if (st != HT_OK) break;
-    ht::set_tuned_shape(h->dtype, h->n, h->m, tc.k, tc.c, tc.form, tc.low, best_shape);
+    ht::set_tuned_shape(h->dtype, h->n, h->m, tc.k, tc.c, tc.form, tc.low, tc.far, best_shape);
     if (nr < max_rows) {
-      double* row = rows + 7 * nr;
+      double* row = rows + 8 * nr;
       row[0] = tc.k;
       row[1] = tc.c;
       row[2] = tc.form;
       row[3] = tc.low;
-      row[4] = best_shape;
-      row[5] = best / (double)ops.size();
-      row[6] = lane_ms / (double)ops.size();
+      row[4] = tc.far;
+      row[5] = best_shape;
+      row[6] = best / (double)ops.size();
+      row[7] = lane_ms / (double)ops.size();
     }
     ++nr;
   }
@@ -200,20 +218,19 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
 }
 
 extern "C" ht_status ht_set_pass_shape(int dtype, int n, int tile_log2, int k, int cross, int form, int low,
-                                       int shape) {
+                                       int far, int shape) {
   if (dtype != HT_C128 && dtype != HT_C64) return ht_fail(HT_EINVAL, "unknown dtype %d", dtype);
   if (n < 1 || n > HT_MAX_QUBITS || tile_log2 < HT_MIN_TILE_LOG2 || tile_log2 > HT_MAX_TILE_LOG2)
     return ht_fail(HT_EINVAL, "invalid n = %d or tile_log2 = %d", n, tile_log2);
   const int m = std::min(n, tile_log2);
+  // far: the highest tile-selecting target at tile bit 4 or above (n - m tile bits)
   if (k < 1 || k > 2 || cross < 0 || cross > k || cross > n - m || form < 0 || form > 1 || low < 0 || low > 1 ||
-      (low == 1 && cross == k))
-    return ht_fail(HT_EINVAL, "no pass class k = %d, cross = %d, form = %d, low = %d at n = %d, m = %d", k, cross,
-                   form, low, n, m);
+      (low == 1 && cross == k) || far < 0 || far > 1 || (far == 1 && (cross == 0 || n - m < 5)))
+    return ht_fail(HT_EINVAL, "no pass class k = %d, cross = %d, form = %d, low = %d, far = %d at n = %d, m = %d",
+                   k, cross, form, low, far, n, m);
   if (shape < -1 || shape >= ht::kShapeCount) return ht_fail(HT_EINVAL, "unknown shape %d", shape);
-  const bool staged = shape >= ht::kShapeStage && shape <= ht::kShapeStage58;
-  const bool steps = shape >= ht::kShapeSync && shape <= ht::kShapeSync58;
-  if ((staged && cross != 0) || (steps && cross == 0))
+  if ((ht::shape_is_stage(shape) && cross != 0) || (ht::shape_is_sync(shape) && cross == 0))
     return ht_fail(HT_EINVAL, "shape %d does not apply to passes with %d tile-selecting targets", shape, cross);
-  ht::set_tuned_shape(dtype, n, m, k, cross, form, low, shape);
+  ht::set_tuned_shape(dtype, n, m, k, cross, form, low, far, shape);
   return HT_OK;
 }

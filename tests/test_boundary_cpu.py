@@ -230,20 +230,24 @@ def test_pass_shape_arguments(ht):
     HT_EINVAL; shape -1 hands a class back to the automatic choice."""
     f = ht.lib.ht_set_pass_shape
     C128, C64 = 0, 1
-    # dtype, n, tile_log2, k, cross, form, low, shape
-    ok = [(C128, 16, 5, 1, 0, 0, 1, 1), (C128, 16, 5, 1, 1, 1, 0, 5), (C64, 16, 5, 2, 2, 0, 0, 6),
-          (C128, 16, 5, 2, 1, 0, 1, 0), (C128, 16, 5, 1, 0, 0, 0, -1), (C64, 9, 3, 2, 0, 1, 1, 3)]
-    bad = [(2, 16, 5, 1, 0, 0, 0, 0),    # unknown dtype
-           (C128, 0, 5, 1, 0, 0, 0, 0),  # n out of range
-           (C128, 16, 9, 1, 0, 0, 0, 0),  # tile_log2 out of range
-           (C128, 16, 5, 3, 0, 0, 0, 0),  # k = 3 has no tuned shapes
-           (C128, 16, 5, 1, 2, 0, 0, 0),  # more tile-selecting targets than targets
-           (C128, 5, 5, 1, 1, 0, 0, 0),   # one tile: no tile-selecting target
-           (C128, 16, 5, 1, 1, 0, 1, 0),  # no intra target, yet "low"
-           (C128, 16, 5, 1, 0, 2, 0, 0),  # form
-           (C128, 16, 5, 1, 1, 0, 0, 1),  # staged shape with a tile-selecting target
-           (C128, 16, 5, 1, 0, 0, 0, 4),  # step shape without one
-           (C128, 16, 5, 1, 0, 0, 0, 7)]  # unknown shape
+    # dtype, n, tile_log2, k, cross, form, low, far, shape
+    ok = [(C128, 16, 5, 1, 0, 0, 1, 0, 1), (C128, 16, 5, 1, 1, 1, 0, 0, 5), (C64, 16, 5, 2, 2, 0, 0, 1, 6),
+          (C128, 16, 5, 2, 1, 0, 1, 0, 0), (C128, 16, 5, 1, 0, 0, 0, 0, -1), (C64, 9, 3, 2, 0, 1, 1, 0, 3),
+          (C128, 16, 5, 1, 1, 0, 0, 1, 12), (C128, 9, 3, 2, 2, 1, 0, 1, 8), (C128, 8, 3, 1, 1, 0, 0, 0, 10)]
+    bad = [(2, 16, 5, 1, 0, 0, 0, 0, 0),    # unknown dtype
+           (C128, 0, 5, 1, 0, 0, 0, 0, 0),  # n out of range
+           (C128, 16, 9, 1, 0, 0, 0, 0, 0),  # tile_log2 out of range
+           (C128, 16, 5, 3, 0, 0, 0, 0, 0),  # k = 3 has no tuned shapes
+           (C128, 16, 5, 1, 2, 0, 0, 0, 0),  # more tile-selecting targets than targets
+           (C128, 5, 5, 1, 1, 0, 0, 0, 0),   # one tile: no tile-selecting target
+           (C128, 16, 5, 1, 1, 0, 1, 0, 0),  # no intra target, yet "low"
+           (C128, 16, 5, 1, 0, 2, 0, 0, 0),  # form
+           (C128, 16, 5, 1, 0, 0, 0, 1, 0),  # far without a tile-selecting target
+           (C128, 7, 3, 1, 1, 0, 0, 1, 0),   # far with tile bits 0..3 only
+           (C128, 16, 5, 1, 1, 0, 0, 2, 0),  # far is 0 or 1
+           (C128, 16, 5, 1, 1, 0, 0, 0, 1),  # staged shape with a tile-selecting target
+           (C128, 16, 5, 1, 0, 0, 0, 0, 4),  # step shape without one
+           (C128, 16, 5, 1, 0, 0, 0, 0, 13)]  # unknown shape
     try:
         for args in ok:
             assert f(*args) == 0, (args, ht.lib.ht_last_error())
@@ -251,4 +255,4 @@ def test_pass_shape_arguments(ht):
             assert f(*args) == 1, args
     finally:
         for args in ok:
-            f(*args[:7], -1)
+            f(*args[:8], -1)

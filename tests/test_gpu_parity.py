@@ -185,10 +185,14 @@ STEP_TUNINGS = [
     {"stage": 1, "stage_threads": 256, "stage_pipe": 1},
     {"stage": 1, "stage_threads": 512, "stage_pipe": 1},
     {"stage": 1, "stage_threads": 256, "stage_pipe": 0},
-    # workgroup-wide steps, both patch orders
-    {"sync_waves": 16},
-    {"sync_waves": 8, "sync_interleave": 0},
-    {"sync_waves": 4, "sync_interleave": 1},
+    # workgroup-wide steps, both patch orders, the three item orders
+    {"sync_waves": 16, "sync_order": 0},
+    {"sync_waves": 8, "sync_interleave": 0, "sync_order": 0},
+    {"sync_waves": 4, "sync_interleave": 1, "sync_order": 0},
+    {"sync_waves": 16, "sync_order": 1},
+    {"sync_waves": 16, "sync_order": 2},
+    {"sync_waves": 8, "sync_order": 2},
+    {"sync_waves": 4, "sync_order": 1, "sync_interleave": 1},
     # complex64 pair passes with two tile-selecting targets in plain mode: one pair per step
     {"pair_jp2": 0},
     # steps with the next one prefetched, with and without the barrier
@@ -197,6 +201,7 @@ STEP_TUNINGS = [
     {"pipe_waves": 8},
 ]
 STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
+                 "sync_order": -1,
                  "pipe_waves": 0, "pipe_barrier": 1, "native": 1, "pair_jp2": 1}
 
 
@@ -270,6 +275,9 @@ def test_pass_tuner_keeps_the_operator_and_the_results(ht, dtype):
     assert (1, 0, "direct", True) in classes and (1, 1, "transfer", False) in classes
     assert (2, 2, "direct", False) in classes and (2, 1, "transfer", True) in classes
     assert all(r["ms"] > 0 and r["lane_ms"] > 0 for r in rows)
+    # tile bits 0..5: both buckets of the highest tile-selecting target
+    assert {(r["cross"], r["far"]) for r in rows if r["k"] == 1} >= {(1, False), (1, True)}
+    assert all(r["shape"] in ht.PASS_SHAPES for r in rows)
     h.close()
     ops = []
     for _ in range(20):

@@ -360,3 +360,39 @@ def test_k3_kraus_form_full_rank_and_permutations(hc):
     n, m = 7, 5
     check_k3(hc, n, m, [6, 1, 5], synth.random_kraus_set(3, 64, rng), False, rng)
     check_k3(hc, n, m, [2, 6, 0], synth.permutation_gate("TOFFOLI")[None], True, rng, native=0)
+
+
+def test_step_kernel_item_orders_cover_every_item_once():
+    """The workgroup-wide step kernel's item orders (sync_item): for every
+    group count, steps per group, waves per workgroup, steps per group in
+    one workgroup step (r) and every-other-group choice, the (unit, wave)
+    pairs reach each (group, step) of the pass exactly once, every step
+    index is in range, and whole groups (r = min(sl, log2 waves), no
+    alternation) are the consecutive items u * waves + w."""
+    if not os.path.exists(SO):
+        pytest.skip("_hostcheck.so not built")
+    f = ctypes.CDLL(SO).htc_sync_items
+    f.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_uint64
+    cap = 4096
+    for ng in (1, 2, 3, 15, 16, 17, 31, 33, 100, 528):
+        for sl in range(5):
+            for lw in (2, 3, 4):
+                wpb = 1 << lw
+                for r in range(min(sl, lw) + 1):
+                    for par in (0, 1):
+                        grp = np.zeros(cap * wpb, dtype=np.uint64)
+                        step = np.zeros(cap * wpb, dtype=np.uint32)
+                        nu = f(ng, sl, wpb, r, par, cap, grp.ctypes.data, step.ctypes.data)
+                        assert 0 < nu <= cap
+                        g, s = grp[:nu * wpb], step[:nu * wpb]
+                        assert np.all(s < (1 << sl))
+                        live = g < ng
+                        key = g[live] * (1 << sl) + s[live]
+                        assert np.array_equal(np.sort(key), np.arange(ng << sl, dtype=np.uint64)), \
+                            (ng, sl, wpb, r, par)
+                        if r == min(sl, lw) and par == 0:
+                            it = np.arange(nu * wpb, dtype=np.uint64)
+                            assert np.array_equal(g, it >> np.uint64(sl))
+                            assert np.array_equal(s, (it & np.uint64((1 << sl) - 1)).astype(np.uint32))
