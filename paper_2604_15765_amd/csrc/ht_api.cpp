@@ -639,6 +639,11 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     (k == "stage_grid" ? ht::tuning().stage_grid : ht::tuning().sync_grid) = (int)value;
     return HT_OK;
   }
+  if (k == "stage_order") {
+    if (value < -1 || value > 1) return ht_fail(HT_EINVAL, "stage_order must be -1, 0 or 1");
+    ht::tuning().stage_order = (int)value;
+    return HT_OK;
+  }
   if (k == "stage_pipe") {
     if (value < 0 || value > 1) return ht_fail(HT_EINVAL, "stage_pipe must be 0 or 1");
     ht::tuning().stage_pipe = (int)value;

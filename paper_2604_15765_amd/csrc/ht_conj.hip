@@ -221,7 +221,13 @@ constexpr int kStageVecs = 16;                 // 16-byte vectors per thread and
 // not for its global loads (a prefetch may stay in flight across it).
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <typename T, int K, int FORM, int kStageThreads, bool PIPE>
+// PAR: a step takes every other 16 KiB granule of twice its span (the
+// other step of the pair the granules in between), so that the granules a
+// workgroup step touches share address bit 14; tiles of at most 16 KiB only
+// (a granule then holds whole tiles).
+constexpr uint32_t kGranVecs = 1024;  // 16-byte vectors per 16 KiB granule
+
+template <typename T, int K, int FORM, int kStageThreads, bool PIPE, bool PAR = false>
 __global__ void __launch_bounds__(kStageThreads)
     stage_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, 0> g, Coef<K, FORM> cf,
                  const double* __restrict__ coef, uint64_t total) {
@@ -230,6 +236,7 @@ __global__ void __launch_bounds__(kStageThreads)
   constexpr uint32_t EPV = 16 / sizeof(S2);                 // entries per vector
   constexpr uint32_t CAPV = kStageVecs * kStageThreads;     // vectors per step
   constexpr uint32_t CAP = CAPV * EPV;                      // entries per step
+  constexpr uint32_t GPS = CAPV / kGranVecs;                // granules per step
   constexpr int D = 1 << K;
   __shared__ u4 lds[CAPV];
   if constexpr (K == 2 && FORM == 1) cf.p = coef;
@@ -237,25 +244,43 @@ __global__ void __launch_bounds__(kStageThreads)
   const int m = g.m;
   const int F = g.F;
   const uint32_t bpt_log = 2u * (uint32_t)F;                // blocks per tile = 4^F
-  const uint64_t nsteps = (total + CAP - 1) / CAP;
+  const uint64_t tv = total / EPV;                          // vectors in the buffer
+  const uint64_t nsteps =
+      PAR ? 2 * ((tv + 2ull * CAPV - 1) / (2ull * CAPV)) : (total + CAP - 1) / CAP;
   u4* __restrict__ hv = reinterpret_cast<u4*>(h);
   S2* le = reinterpret_cast<S2*>(lds);
-  // vectors of step st that lie in the buffer (whole tiles; the last step may be short)
+  // first granule of step st (PAR)
+  auto gran0 = [&](uint64_t st) -> uint64_t { return (st >> 1) * (2ull * GPS) + (st & 1u); };
+  // buffer vector of the step's i-th vector
+  auto vaddr = [&](uint64_t st, uint32_t i) -> uint64_t {
+    if constexpr (PAR) return (gran0(st) + 2ull * (i / kGranVecs)) * kGranVecs + (i % kGranVecs);
+    return st * CAPV + i;
+  };
+  // vectors of step st that lie in the buffer (whole tiles; they form a
+  // prefix of the step's vectors, since only the buffer's last granule can
+  // be partial)
   auto count_v = [&](uint64_t st) -> uint32_t {
+    if constexpr (PAR) {
+      uint32_t c = 0;
+      for (uint32_t i = 0; i < GPS; ++i) {
+        const uint64_t g0 = (gran0(st) + 2ull * i) * kGranVecs;
+        if (g0 < tv) c += (tv - g0 < kGranVecs) ? (uint32_t)(tv - g0) : kGranVecs;
+      }
+      return c;
+    }
     const uint64_t left = total - st * CAP;
     return (left < CAP ? (uint32_t)left : CAP) / EPV;
   };
   auto load_step = [&](uint64_t st, u4 (&v)[kStageVecs]) {
-    const u4* src = hv + st * CAPV;
     const uint32_t cntv = count_v(st);
     if (cntv == CAPV) {
 #pragma unroll
-      for (int j = 0; j < kStageVecs; ++j) v[j] = __builtin_nontemporal_load(src + j * kStageThreads + t);
+      for (int j = 0; j < kStageVecs; ++j) v[j] = __builtin_nontemporal_load(hv + vaddr(st, j * kStageThreads + t));
     } else {
 #pragma unroll
       for (int j = 0; j < kStageVecs; ++j) {
         const uint32_t i = j * kStageThreads + t;
-        if (i < cntv) v[j] = __builtin_nontemporal_load(src + i);
+        if (i < cntv) v[j] = __builtin_nontemporal_load(hv + vaddr(st, i));
       }
     }
   };
@@ -303,18 +328,17 @@ __global__ void __launch_bounds__(kStageThreads)
       });
     }
     lds_barrier();
-    u4* dst = hv + st * CAPV;
     if (cntv == CAPV) {
       u4 o[kStageVecs];
 #pragma unroll
       for (int j = 0; j < kStageVecs; ++j) o[j] = lds[j * kStageThreads + t];
 #pragma unroll
-      for (int j = 0; j < kStageVecs; ++j) __builtin_nontemporal_store(o[j], dst + j * kStageThreads + t);
+      for (int j = 0; j < kStageVecs; ++j) __builtin_nontemporal_store(o[j], hv + vaddr(st, j * kStageThreads + t));
     } else {
 #pragma unroll
       for (int j = 0; j < kStageVecs; ++j) {
         const uint32_t i = j * kStageThreads + t;
-        if (i < cntv) __builtin_nontemporal_store(lds[i], dst + i);
+        if (i < cntv) __builtin_nontemporal_store(lds[i], hv + vaddr(st, i));
       }
     }
   }
@@ -515,13 +539,28 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       if (shape >= 0) sw = shape_grid(shape, num_cu);
       if (sw > steps_total) sw = steps_total;
       const bool pipe = tuning().stage_pipe != 0;
-#define HT_STAGE(TH, P)                                                                                   \
-  hipLaunchKernelGGL((stage_kernel<T, K, FORM, TH, P>), dim3((unsigned)sw), dim3(TH), 0, s, hp, g, cf,   \
+      // Every other 16 KiB granule per step (tiles of at most 16 KiB).
+      // Measured at n = 16, c128 on one device: contiguous steps 5.17-5.33
+      // TB/s for every intra class (4.4-4.8 at 3/4 and 5/8 of a workgroup
+      // per CU), alternate granules 5.9-6.0 (6.12-6.14 at 3/4 for k = 1);
+      // contiguous steps reached 6.05 on other devices.
+      int sord = tuning().stage_order;
+      if (shape >= 0) sord = shape_stage_order(shape);
+      if (sord < 0) sord = 1;
+      const bool par = sord == 1 && tile_bytes <= 16384;
+#define HT_STAGE(TH, P, Q)                                                                                \
+  hipLaunchKernelGGL((stage_kernel<T, K, FORM, TH, P, Q>), dim3((unsigned)sw), dim3(TH), 0, s, hp, g, cf, \
                      coef_dev, nent)
-      if (sth == 512) {
-        if (pipe) HT_STAGE(512, true); else HT_STAGE(512, false);
+      if (par) {
+        if (sth == 512) {
+          if (pipe) HT_STAGE(512, true, true); else HT_STAGE(512, false, true);
+        } else {
+          if (pipe) HT_STAGE(256, true, true); else HT_STAGE(256, false, true);
+        }
+      } else if (sth == 512) {
+        if (pipe) HT_STAGE(512, true, false); else HT_STAGE(512, false, false);
       } else {
-        if (pipe) HT_STAGE(256, true); else HT_STAGE(256, false);
+        if (pipe) HT_STAGE(256, true, false); else HT_STAGE(256, false, false);
       }
 #undef HT_STAGE
       return hipGetLastError();

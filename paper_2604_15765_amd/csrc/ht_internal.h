@@ -38,6 +38,8 @@ struct LaunchTuning {
   int stage_grid = 0;       // staged pass: workgroups of the grid (0: stage_wg_per_cu per CU)
   int sync_grid = 0;        // synchronised pass: workgroups of the grid (0: sync_wg_per_cu per CU)
   int stage_pipe = 1;      // staged pass: prefetch the next step during compute
+  int stage_order = -1;     // staged pass: -1 automatic, 0 contiguous steps, 1 every other 16 KiB
+                            // granule per step
   int stage_threads = 512;  // threads per workgroup of the staged pass (256: 64 KiB steps, 512: 128 KiB)
   int sync_waves = -1;      // passes with a tile-selecting target in workgroup-wide
                             // steps: -1 automatic, 0 off, else waves per workgroup (4, 8, 16)
@@ -60,19 +62,26 @@ LaunchTuning& tuning();
 // tile of 16 consecutive groups, and one quarter of every other group.
 enum PassShape {
   kShapeLane = 0,      // lane-patch kernel (conj_kernel), automatic grid
-  kShapeStage = 1,     // LDS-staged intra-tile pass, 3 grids (1..3)
+  kShapeStage = 1,     // LDS-staged intra-tile pass, contiguous steps, 3 grids (1..3)
   kShapeSync = 4,      // 16-wave workgroup steps, whole groups (4..6)
   kShapeSyncQ = 7,     //   ... quarters of consecutive groups (7..9)
   kShapeSyncQA = 10,   //   ... quarters of every other group (10..12)
-  kShapeCount = 13
+  kShapeStageA = 13,   // LDS-staged pass, every other 16 KiB granule per step (13..15)
+  kShapeCount = 16
 };
-inline bool shape_is_stage(int shape) { return shape >= kShapeStage && shape < kShapeSync; }
-inline bool shape_is_sync(int shape) { return shape >= kShapeSync && shape < kShapeCount; }
+inline bool shape_is_stage(int shape) {
+  return (shape >= kShapeStage && shape < kShapeSync) || (shape >= kShapeStageA && shape < kShapeCount);
+}
+inline bool shape_is_sync(int shape) { return shape >= kShapeSync && shape < kShapeStageA; }
 // Item order of a step shape: 0 whole groups, 1 quarters, 2 quarters of every other group.
 inline int shape_sync_order(int shape) { return (shape - kShapeSync) / 3; }
+// Step order of a staged shape: 0 contiguous, 1 every other 16 KiB granule.
+inline int shape_stage_order(int shape) { return shape >= kShapeStageA ? 1 : 0; }
 // Grid of a shape: workgroups for num_cu compute units.
 inline uint64_t shape_grid(int shape, int num_cu) {
-  const int i = shape_is_stage(shape) ? shape - kShapeStage : shape_is_sync(shape) ? (shape - kShapeSync) % 3 : 0;
+  const int i = shape_is_stage(shape) ? (shape - (shape >= kShapeStageA ? kShapeStageA : kShapeStage))
+                : shape_is_sync(shape) ? (shape - kShapeSync) % 3
+                                       : 0;
   const int f = i == 1 ? 6 : i == 2 ? 5 : 8;
   return (uint64_t)num_cu * (uint64_t)f / 8u;
 }

@@ -148,10 +148,9 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
     // the class's sorted targets all share ncross == tc.c by construction
     const bool skip_stage = h->dtype == HT_C64 && tc.k == 2 && tc.form == 1;  // measured 7x slower staged
     std::vector<int> cands = {ht::kShapeLane};
-    if (tc.c == 0 && !skip_stage)
-      for (int sh = ht::kShapeStage; sh < ht::kShapeSync; ++sh) cands.push_back(sh);
-    if (tc.c > 0)
-      for (int sh = ht::kShapeSync; sh < ht::kShapeCount; ++sh) cands.push_back(sh);
+    for (int sh = 1; sh < ht::kShapeCount; ++sh)
+      if ((tc.c == 0 && !skip_stage && ht::shape_is_stage(sh)) || (tc.c > 0 && ht::shape_is_sync(sh)))
+        cands.push_back(sh);
     double best = 1e300, lane_ms = 0.0;
     int best_shape = ht::kShapeLane;
     for (int shape : cands) {
@@ -159,6 +158,7 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
       ht::tuning().pipe_waves = 0;
       ht::tuning().stage = ht::shape_is_stage(shape) ? 1 : 0;
       ht::tuning().stage_grid = ht::tuning().stage ? (int)ht::shape_grid(shape, h->num_cu) : 0;
+      ht::tuning().stage_order = ht::tuning().stage ? ht::shape_stage_order(shape) : -1;
       ht::tuning().sync_waves = ht::shape_is_sync(shape) ? 16 : 0;
       ht::tuning().sync_grid = ht::tuning().sync_waves ? (int)ht::shape_grid(shape, h->num_cu) : 0;
       ht::tuning().sync_order = ht::tuning().sync_waves ? ht::shape_sync_order(shape) : -1;

@@ -185,6 +185,9 @@ STEP_TUNINGS = [
     {"stage": 1, "stage_threads": 256, "stage_pipe": 1},
     {"stage": 1, "stage_threads": 512, "stage_pipe": 1},
     {"stage": 1, "stage_threads": 256, "stage_pipe": 0},
+    # ... every other 16 KiB granule per step
+    {"stage": 1, "stage_threads": 512, "stage_pipe": 1, "stage_order": 1},
+    {"stage": 1, "stage_threads": 256, "stage_pipe": 0, "stage_order": 1},
     # workgroup-wide steps, both patch orders, the three item orders
     {"sync_waves": 16, "sync_order": 0},
     {"sync_waves": 8, "sync_interleave": 0, "sync_order": 0},
@@ -201,7 +204,7 @@ STEP_TUNINGS = [
     {"pipe_waves": 8},
 ]
 STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
-                 "sync_order": -1,
+                 "sync_order": -1, "stage_order": -1,
                  "pipe_waves": 0, "pipe_barrier": 1, "native": 1, "pair_jp2": 1}
 
 
