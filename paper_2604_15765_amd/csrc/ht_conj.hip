@@ -208,13 +208,14 @@ __global__ void __launch_bounds__(NTH)
 
 // Intra-tile passes (Algorithm 2: every target inside the tile, every stored
 // tile handled alike, diagonal tiles in both halves) staged through LDS.
-// Tiles are contiguous in storage, so a workgroup step takes the next 64 KiB
-// of the buffer -- 4096 / M^2 whole tiles of 16-byte entries, twice as many
-// of 8-byte ones -- with 1 KiB nontemporal loads per wave instruction, puts
-// it in LDS, applies the operation to every block of those tiles out of LDS,
-// and writes the 64 KiB back the same way.  Global accesses are whole lines
-// whatever the target bits; the block arithmetic is that of conj_kernel
-// (block_apply), so results are bitwise the same.
+// Tiles are contiguous in storage, so a workgroup step takes 16 KiB per
+// wave of the threads (64 or 128 KiB: whole tiles of at most that size) --
+// the next contiguous run of the buffer, or (PAR) every other 16 KiB
+// granule of twice that span -- with 1 KiB nontemporal loads per wave
+// instruction, puts it in LDS, applies the operation to every block of
+// those tiles out of LDS, and writes it back the same way.  Global
+// accesses are whole lines whatever the target bits; the block arithmetic
+// is that of conj_kernel (block_apply), so results are bitwise the same.
 constexpr int kStageVecs = 16;                 // 16-byte vectors per thread and step
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
@@ -497,16 +498,15 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   if (wgs > cap) wgs = cap;
   if (wgs < 1) wgs = 1;
   auto* hp = reinterpret_cast<typename store2<T>::type*>(buf);
-  // Lowest intra target (none: 99).  Automatic choices for complex128
-  // operators of 1 GiB and more, measured at n = 16 (TB/s of algorithmic
-  // traffic, before -> after): intra-tile passes staged through LDS in
-  // 128 KiB steps with the next step prefetched run every target at about
-  // 5.7 (4.9-5.6 before; two-qubit direct passes whose targets are all at
-  // bit 3 or above stay on the lane-patch kernel, 5.8 there); passes with a
-  // tile-selecting target take workgroup-wide steps of 16 waves, 4 groups
-  // per step (5.05-5.2 -> 5.2-5.35), two tile-selecting targets with
-  // row-run patches (interleave 0); an intra target below bit 3 beside a
-  // tile-selecting one stays on the lane-patch kernel (slower in steps).
+  // Lowest intra target (none: 99).  Automatic choices for operators of
+  // 1 GiB and more, measured at n = 16 (TB/s of algorithmic traffic):
+  // intra-tile passes staged through LDS in 128 KiB steps of alternate
+  // 16 KiB granules with the next step prefetched (c128 5.9-6.15, the
+  // lane-patch kernel 4.7-5.7); complex128 passes with a tile-selecting
+  // target in workgroup-wide steps of 16 waves whose item order follows the
+  // target's tile bit (5.45-5.87, whole groups 5.2-5.5); an intra target
+  // below bit 3 beside a tile-selecting one, and one intra beside one
+  // tile-selecting target, stay on the lane-patch kernel.
   constexpr int KI = K - C;
   const int low = KI > 0 ? g.ipos[0] : 99;
   // highest tile-selecting target at tile bit 4 or above
@@ -524,10 +524,7 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       // kernels ran 4.3-5.2 TB/s there, staged 5.0-5.75), except its k = 2
       // transfer form, whose 16 x 16 matrix the staged pass reads far slower
       const bool large = nent * 2 * sizeof(T) >= (1ull << 30);
-      stage = large && !(sizeof(T) == 8 && K == 2 && FORM == 0 && low >= 3) &&
-                      !(sizeof(T) == 4 && K == 2 && FORM == 1)
-                  ? 1
-                  : 0;
+      stage = large && !(sizeof(T) == 4 && K == 2 && FORM == 1) ? 1 : 0;
     }
     if (shape >= 0) stage = shape_is_stage(shape) ? 1 : 0;
     const int sth = tuning().stage_threads;
@@ -623,7 +620,10 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       if (r < 0) r = 0;
       const int par = ord == 2 ? 1 : 0;
       uint64_t wg = sync_units(g.ngroups, sl, (uint32_t)sw, r, par);
+      // grid: the quarter orders at 3/4 of a workgroup per CU (measured
+      // 1-4 % faster than one per CU at most tile bits)
       uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
+                      : ord != 0             ? (uint64_t)num_cu * 3u / 4u
                                              : (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
       if (shape >= 0) wcap = shape_grid(shape, num_cu);
       if (wg > wcap) wg = wcap;

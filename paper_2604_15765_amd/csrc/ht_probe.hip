@@ -21,7 +21,14 @@
 //                    back) instead of in registers;
 //   xstage<NS>       512 threads move 128 KiB per step through LDS, as NS
 //                    runs in NS regions, with the next step's loads issued
-//                    before the current step is updated and stored.
+//                    before the current step is updated and stored;
+//   colour<MODE>     in-place (MODE 0), read-only (1) or write-only (2)
+//                    streams of 1 KiB units, where a workgroup step takes
+//                    64 units that share a "colour": bits [g, g + cbits) of
+//                    the unit index equal bits [sel, sel + cbits) of the
+//                    workgroup index (g = 2, cbits = 3: the 4 KiB runs of a
+//                    step share address bits 12-14; cbits = 0: contiguous
+//                    64 KiB per step).
 // Every kernel is a grid-stride loop over whole work items that lie inside
 // the buffer (items that would cross its end are not formed).
 #include <hip/hip_runtime.h>
@@ -205,6 +212,49 @@ __global__ void __launch_bounds__(512) xstage(u4* __restrict__ p, uint64_t n16, 
   }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(256) colour(u4* __restrict__ p, uint64_t nunits, int g, int cbits, int sel,
+                                              unsigned salt, u4* __restrict__ sink) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t b = blockIdx.x;
+  const uint32_t col = (b >> sel) & ((1u << cbits) - 1u);
+  // workgroups of one colour, numbered without the colour bits
+  const uint64_t lw = ((uint64_t)(b >> (sel + cbits)) << sel) | (b & ((1u << sel) - 1u));
+  const uint64_t lg = gridDim.x >> cbits;
+  const uint64_t steps = (nunits >> cbits) / 64;
+  u4 acc = {0, 0, 0, 0};
+  for (uint64_t st = lw; st < steps; st += lg) {
+    u4 v[16];
+    uint64_t off[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint64_t k = st * 64 + wave * 16 + i;  // unit within the colour
+      const uint64_t u = ((k >> g) << (g + cbits)) | ((uint64_t)col << g) | (k & ((1ull << g) - 1));
+      off[i] = u * 64 + lane;
+    }
+    if constexpr (MODE != 2) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = __builtin_nontemporal_load(p + off[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = u4{salt, (unsigned)i, 0u, salt};
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc ^= v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        v[i].x ^= salt;
+        v[i].w += salt;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(v[i], p + off[i]);
+    }
+  }
+  if constexpr (MODE == 1) sink[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -295,6 +345,26 @@ int htp_write(void* buf, uint64_t n16, int grid, void* stream) {
 int htp_copy(void* dst, const void* src, uint64_t n16, int grid, void* stream) {
   hipLaunchKernelGGL(copy_stream, dim3(grid), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                      reinterpret_cast<u4*>(dst), reinterpret_cast<const u4*>(src), n16);
+  return (int)hipGetLastError();
+}
+
+// buf: nunits 1 KiB units; sink: grid x 256 16-byte words (read-only mode).
+// HIP's invalid-value error for shapes the colouring cannot cover exactly.
+int htp_colour(int mode, void* buf, uint64_t nunits, int g, int cbits, int sel, int grid, void* sink,
+               void* stream) {
+  if (mode < 0 || mode > 2 || cbits < 0 || cbits > 6 || g < 0 || g > 20 || sel < 0 || sel + cbits > 12 ||
+      grid <= 0 || (grid >> (sel + cbits)) == 0 || grid % (1 << (sel + cbits)) != 0 ||
+      nunits % (64ull << (g + cbits)) != 0)
+    return (int)hipErrorInvalidValue;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  u4* p = reinterpret_cast<u4*>(buf);
+  u4* sk = reinterpret_cast<u4*>(sink);
+  if (mode == 0)
+    hipLaunchKernelGGL(colour<0>, dim3(grid), dim3(256), 0, s, p, nunits, g, cbits, sel, 7u, sk);
+  else if (mode == 1)
+    hipLaunchKernelGGL(colour<1>, dim3(grid), dim3(256), 0, s, p, nunits, g, cbits, sel, 7u, sk);
+  else
+    hipLaunchKernelGGL(colour<2>, dim3(grid), dim3(256), 0, s, p, nunits, g, cbits, sel, 7u, sk);
   return (int)hipGetLastError();
 }
 

@@ -29,10 +29,15 @@ KERNEL_SOURCES = ("csrc/ht_geom.h", "csrc/ht_conj.hip")
 
 
 def source_fingerprint() -> str:
+    """Hash of the kernel sources without their comments and blank lines
+    (an edit of a comment leaves the profiled kernels as they were)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 
@@ -47,7 +52,8 @@ def _csv(d, suffix):
 def kernel_class(name: str):
     """'conj_kernel<double, 1, 1, 0, 0>' -> 'c128_k1_c1_direct' (also the
     workgroup-step kernels conj_sync_kernel and conj_pipe_kernel),
-    'stage_kernel<double, 2, 1, 512, true>' -> 'c128_k2_c0_transfer',
+    'stage_kernel<double, 2, 1, 512, true>' -> 'c128_k2_c0_transfer' (also
+    with the granule-order flag, 'stage_kernel<double, 2, 1, 512, true, true>'),
     'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
     'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus',
     'pair_kernel<1, 1, 0, 3, 2>' -> 'c64_k1_c1_direct' (complex64 only); None
@@ -56,7 +62,7 @@ def kernel_class(name: str):
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k{m.group(2)}_c{m.group(3)}_{'direct' if m.group(4) == '0' else 'transfer'}"
-    m = re.search(r"stage_kernel<(double|float), (\d), (\d), \d+, (?:true|false)>", name)
+    m = re.search(r"stage_kernel<(double|float), (\d), (\d), \d+, (?:true|false)(?:, (?:true|false))?>", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k{m.group(2)}_c0_{'direct' if m.group(3) == '0' else 'transfer'}"

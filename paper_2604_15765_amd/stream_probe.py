@@ -8,7 +8,8 @@ JSON line: read-only, write-only and copy bandwidth, and in-place
 read-modify-write bandwidth for 1, 2, 4 and 16 concurrent far-apart streams,
 with and without nontemporal hints, and in-place tile-by-tile streams of
 16 KiB tiles with contiguous and with 8 x 8-patch instructions, each the best
-over a few grid sizes.
+over a few grid sizes; workgroup read and write bursts; and "colourings", in
+which the 1 KiB runs that a workgroup step moves share a few address bits.
 Bandwidth counts bytes read plus bytes written.
 """
 
@@ -88,6 +89,18 @@ def main():
         for g in (256, 192):
             r[f"xstage_{ns}regions_grid{g}_GBps"] = best_of(
                 lambda g_, ns=ns: lib.htp_xstage(ns, vp(a.data_ptr()), u64(n16), g_, st), moved, (g,))
+    # colourings of 1 KiB units (every unit moved once; 256 workgroups)
+    nunits = (nb // 1024) // (64 << 10) * (64 << 10)
+    sink = torch.empty(256 * 256 * 16, dtype=torch.uint8, device="cuda")
+    for name, g, cb, sel in (("contiguous", 0, 0, 0), ("bits10-12", 0, 3, 0), ("bits11-13", 1, 3, 0),
+                             ("bits12-14", 2, 3, 0), ("bits12-14_not_by_xcd", 2, 3, 3), ("bits13-15", 3, 3, 0),
+                             ("bits14-16", 4, 3, 0), ("bits12-13", 2, 2, 0), ("bit14", 4, 1, 0),
+                             ("bit15", 5, 1, 0)):
+        for mode, tag, moved in ((0, "rmw", 2 * nunits * 1024), (1, "read", nunits * 1024)):
+            r[f"colour_{name}_{tag}_GBps"] = best_of(
+                lambda g_, mode=mode, g=g, cb=cb, sel=sel: lib.htp_colour(
+                    mode, vp(a.data_ptr()), u64(nunits), g, cb, sel, g_, vp(sink.data_ptr()), st),
+                moved, (256,))
     print(json.dumps(r), flush=True)
     if args.summary:
         write_summary(r, args.summary)
@@ -114,6 +127,9 @@ def write_summary(r: dict, path: str) -> None:
         "#   _lds: through LDS; best of grids 256/192 workgroups",
         "# xstage_<S>regions_grid<G>: 512 threads move 128 KiB per step through LDS in S runs, next step "
         "prefetched; G workgroups",
+        "# colour_<bits>_<rmw|read>: 256 workgroups, each step 64 units of 1 KiB whose unit-index bits equal "
+        "bits of the workgroup index (the XCD's, unless not_by_xcd):",
+        "#   the named address bits are then equal across a workgroup step; contiguous = 64 KiB per step",
         "",
     ]
     for k, v in r.items():

@@ -18,6 +18,8 @@ def test_kernel_class():
         "ht::conj_pipe_kernel<double, 2, 2, 0, 3, 512, true>": "c128_k2_c2_direct",
         "ht::stage_kernel<double, 1, 0, 512, true>": "c128_k1_c0_direct",
         "ht::stage_kernel<float, 2, 1, 256, false>": "c64_k2_c0_transfer",
+        "ht::stage_kernel<double, 1, 1, 512, true, true>": "c128_k1_c0_transfer",
+        "ht::stage_kernel<float, 2, 0, 512, false, true>": "c64_k2_c0_direct",
         "ht::trace_partial_kernel<double>": None,
         "ht::batch_kernel<float>": None,
     }
