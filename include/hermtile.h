@@ -549,7 +549,8 @@ const char* ht_kernel_class_name(int idx);
  * "stage_order" (-1 automatic, 0 contiguous steps, 1 every other 16 KiB
  * granule per step), "sync_interleave" (-1, 0, 1), "sync_order" (-1 automatic; 0 a workgroup
  * step takes whole groups, 1 one quarter of every tile of consecutive
- * groups, 2 the same of every other group), "pipe_waves" (0, 4, 8: steps with the next
+ * groups, 2 the same of every other group, 3 of every fourth group in the
+ * complex64 pair layout, else as 2), "pipe_waves" (0, 4, 8: steps with the next
  * one prefetched), "pipe_barrier" (0 or 1), "pair_jp2" (0 or 1, default 1:
  * complex64 pair passes with two tile-selecting targets in plain mode take
  * two pairs per step).  A shape tuned by ht_tune_passes is used only while
@@ -565,9 +566,10 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  * an intra target below bit 3 or not, the highest tile-selecting target
  * below tile bit 4 or not -- this times each candidate shape (the
  * lane-patch kernel; the LDS-staged intra-tile pass in two step orders or
- * 16-wave workgroup steps in three item orders, each at grids of 1, 3/4 and
- * 5/8 workgroups per CU) on identity passes of h, reps timed rounds after
- * one warm-up round, and keeps the
+ * workgroup steps in three item orders, four for complex64 (in the pair
+ * layout where it applies), each at grids of 1, 3/4 and 5/8 workgroups per
+ * CU) on identity passes of h, reps timed rounds after one warm-up round,
+ * and keeps the
  * fastest for operators of that shape.  The choice is process-wide and is
  * used while the launch tuning (ht_set_tuning "stage", "sync_waves",
  * "pipe_waves") is automatic; every shape computes bitwise the same result.
@@ -582,8 +584,9 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  * patch, 1-3 staged at 1, 3/4, 5/8 workgroups per CU, 4-6 workgroup steps
  * of whole groups at the same grids, 7-9 steps of one quarter of every tile
  * of 16 groups, 10-12 the same of every other group of 32, 13-15 staged
- * with every other 16 KiB granule per step), its ms per pass, the
- * lane-patch kernel's ms per pass;
+ * with every other 16 KiB granule per step, 16-18 steps of every fourth
+ * group, complex64 only), its ms per pass, the lane-patch kernel's ms per
+ * pass;
  * nrows (may be NULL): classes tuned.  HT_EINVAL for a NULL handle, reps
  * outside [1, 16] or rows NULL with max_rows > 0.  Call it while no other
  * thread enqueues passes (it switches the process-wide launch tuning). */

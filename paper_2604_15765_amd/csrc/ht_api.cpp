@@ -671,7 +671,7 @@ ht_status ht_set_tuning(const char* name, int64_t value) {
     return HT_OK;
   }
   if (k == "sync_order") {
-    if (value < -1 || value > 2) return ht_fail(HT_EINVAL, "sync_order must be -1, 0, 1 or 2");
+    if (value < -1 || value > 3) return ht_fail(HT_EINVAL, "sync_order must be in [-1, 3]");
     ht::tuning().sync_order = (int)value;
     return HT_OK;
   }

@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256)
 template <typename T, int K, int C, int FORM, int MODE>
 __global__ void __launch_bounds__(1024)
     conj_sync_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf,
-                     const double* __restrict__ coef, int r, int par) {
+                     const double* __restrict__ coef, int r, int ps) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wpb = blockDim.x >> 6;
@@ -85,13 +85,13 @@ __global__ void __launch_bounds__(1024)
   constexpr int D = 1 << K;
   const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
   const int sl = 31 - __builtin_clz(steps);
-  const uint64_t nu = sync_units(g.ngroups, sl, wpb, r, par);
+  const uint64_t nu = sync_units(g.ngroups, sl, wpb, r, ps);
   const uint32_t nblk = 1u << (2 * g.F);
   // the loop bound is the same for every wave of the workgroup (barrier)
   for (uint64_t u = blockIdx.x; u < nu; u += gridDim.x) {
     uint64_t grp;
     uint32_t step;
-    sync_item(u, wib, wpb, sl, r, par, grp, step);
+    sync_item(u, wib, wpb, sl, r, ps, grp, step);
     const bool valid = grp < g.ngroups;
     GroupCtx<C> gc;
     group_ctx<K, C>(valid ? grp : 0, g, gc);
@@ -466,6 +466,124 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The pair layout in workgroup-wide steps (complex64): the waves of a
+// workgroup take (group, step) items in the order of sync_item, load their
+// pairs, meet at a barrier, then update and store, as conj_sync_kernel does
+// for the block layout.  Groups on the reduced-grid diagonal keep the block
+// layout (their ownership rules pair blocks (p, q) and (q, p)); they are
+// skipped here and done by pair_diag_kernel, so that this kernel holds only
+// the pair path's registers.  Same arithmetic as pair_kernel: bitwise the
+// same results.
+template <int K, int C, int FORM, int MODE, int JP, int NTH>
+__global__ void __launch_bounds__(NTH)
+    pair_sync_kernel(float2* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf, int r, int ps) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr uint32_t wpb = NTH / 64;
+  const PairMem<MODE, K == 2> pm{h};
+  using PM = PairMem<MODE, K == 2>;
+  static_assert(K == 1 || FORM == 0, "two-qubit pair passes take the direct form");
+  const uint32_t steps = pair_jobs(g.F) / JP;  // a power of two
+  const int sl = 31 - __builtin_clz(steps);
+  const uint64_t nu = sync_units(g.ngroups, sl, wpb, r, ps);
+  // the loop bound is the same for every wave of the workgroup (barrier)
+  for (uint64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    uint64_t grp;
+    uint32_t step;
+    sync_item(u, wib, wpb, sl, r, ps, grp, step);
+    GroupCtx<C> gc;
+    group_ctx<K, C>(grp < g.ngroups ? grp : 0, g, gc);
+    const bool pair = grp < g.ngroups && !gc.diag;
+    PairStep<JP, K, PM> st;
+    if (pair) pair_load<JP, K, C>(pm, g, gc, lane, step * JP, st);
+    __syncthreads();
+    if (pair) pair_update_store<JP, K, C, FORM>(pm, g, gc, cf, st);
+  }
+}
+
+// The reduced-grid diagonal groups (Ti = Tj: group Ti (Ti + 3) / 2) of a
+// pair pass in the block layout, one group per wave.
+template <int K, int C, int FORM, int MODE>
+__global__ void __launch_bounds__(256)
+    pair_diag_kernel(float2* __restrict__ h, ConjGeom<K, C> g, Coef<K, FORM> cf, uint64_t nts) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const DirectMem<float, MODE, K == 1> mem{h};
+  for (uint64_t ti = wave; ti < nts; ti += nwaves) {
+    GroupCtx<C> gc;
+    group_ctx<K, C>(diag_group(ti), g, gc);
+    // only groups that the pair path skips (C > 0: every Ti = Tj group)
+    if (gc.diag) conj_group_lane<conj_unroll(K, 8), K, C, FORM>(mem, g, gc, cf, lane);
+  }
+}
+
+// Memory mode of a complex64 pair pass: nontemporal, except where a
+// quarter or more of the groups hold a mirrored tile (every target
+// tile-selecting, the highest at bit n - 3 or above; see launch_t).
+template <int K, int C>
+static int smode_pair(const ConjGeom<K, C>& g, int n) {
+  int pmode = tuning().mem_mode;
+  if (pmode < 0) {
+    pmode = 3;
+    if constexpr (K - C == 0)
+      if (g.cpos[C - 1] + g.m >= n - 3) pmode = 0;
+  }
+  return pmode;
+}
+
+// Launch pair_sync_kernel and pair_diag_kernel: item order from the shape,
+// the tuning or (-1) whole groups; the quarter orders give a workgroup step
+// the steps that share the tile's top row bit (the pair patches' last job
+// bit) and take every group, every other one or every fourth.  16 waves per
+// workgroup for k = 1; k = 2 (above 128 registers) takes 8.
+template <int K, int C, int FORM>
+static hipError_t launch_pair_sync(float2* hp, const ConjGeom<K, C>& g, const Coef<K, FORM>& cf, int shape,
+                                   int pmode, int num_cu, hipStream_t s) {
+  constexpr int NTH = K == 1 ? 1024 : 512;
+  constexpr uint32_t wpb = NTH / 64;
+  // two pairs per lane and step for k = 1; one for k = 2 (two would spill)
+  constexpr int jp = K == 1 ? 2 : 1;
+  // automatic: every fourth group for k = 1 (measured at n = 16, tile bits
+  // 0-5: 5.8-5.9 TB/s against 5.0-5.3 for pair_kernel), whole groups else
+  int ord = tuning().sync_order;
+  if (shape >= 0) ord = shape_sync_order(shape);
+  if (ord < 0) ord = K == 1 ? 3 : 0;
+  int sl, r, ps;
+  pair_sync_order(g.F, jp, 31 - __builtin_clz(wpb), ord, sl, r, ps);
+  uint64_t wg = sync_units(g.ngroups, sl, wpb, r, ps);
+  // one workgroup per CU (measured 1-3 % faster than 3/4 in every order)
+  uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
+                                         : (uint64_t)num_cu * (uint64_t)tuning().sync_wg_per_cu;
+  if (shape >= 0) wcap = shape_grid(shape, num_cu);
+  if (wg > wcap) wg = wcap;
+  const dim3 grid((unsigned)wg), block(NTH);
+#define HT_PS(M_, J_) \
+  hipLaunchKernelGGL((pair_sync_kernel<K, C, FORM, M_, J_, NTH>), grid, block, 0, s, hp, g, cf, r, ps)
+  switch (pmode) {
+    case 1: HT_PS(1, jp); break;
+    case 2: HT_PS(2, jp); break;
+    case 3: HT_PS(3, jp); break;
+    default: HT_PS(0, jp);
+  }
+#undef HT_PS
+  hipError_t e = hipGetLastError();
+  // intra-tile passes (C = 0) have no diagonal groups: the pair path takes
+  // diagonal tiles like any other
+  if (e != hipSuccess || C == 0) return e;
+  const uint64_t nts = grid_rows(g.ngroups);
+  const unsigned dg = (unsigned)((nts + 3) / 4 < (uint64_t)num_cu ? (nts + 3) / 4 : (uint64_t)num_cu);
+#define HT_PD(M_) hipLaunchKernelGGL((pair_diag_kernel<K, C, FORM, M_>), dim3(dg), dim3(256), 0, s, hp, g, cf, nts)
+  switch (pmode) {
+    case 1: HT_PD(1); break;
+    case 2: HT_PD(2); break;
+    case 3: HT_PD(3); break;
+    default: HT_PD(0);
+  }
+#undef HT_PD
+  return hipGetLastError();
+}
+
 template <typename T, int K, int C, int FORM>
 static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const double* coef_dev,
                            int num_cu, hipStream_t s) {
@@ -591,9 +709,18 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   {
     // workgroup-wide steps
     int sw = tuning().sync_waves;
-    if (sw < 0) sw = (big && C > 0 && low >= 3 && !(K == 2 && C == 1)) ? 16 : 0;
+    // complex64 of 1 GiB and more: one-qubit passes with a tile-selecting
+    // target in the pair layout's steps (pair_sync_kernel)
+    const bool big64 = sizeof(T) == 4 && nent * 2 * sizeof(T) >= (1ull << 30);
+    const bool pairs64 = big64 && K == 1 && C == 1 && g.F >= 4 && tuning().pairs != 0;
+    if (sw < 0) sw = ((big && C > 0 && low >= 3 && !(K == 2 && C == 1)) || pairs64) ? 16 : 0;
     if (shape >= 0) sw = (C > 0 && shape_is_sync(shape)) ? 16 : 0;
     if (sw > 0) {
+      // complex64 where the pair layout applies: the pair step kernel
+      if constexpr (sizeof(T) == 4 && (K == 1 || FORM == 0)) {
+        const bool pl = g.F >= 4 && (KI == 0 || g.ipos[0] != 0) && tuning().pairs != 0;
+        if (pl) return launch_pair_sync<K, C, FORM>(hp, g, cf, shape, smode_pair(g, n), num_cu, s);
+      }
       ConjGeom<K, C> gs = g;
       // Item order.  Measured at n = 16, c128 (TB/s of algorithmic traffic,
       // whole groups -> quarters -> quarters of every other group): k = 1
@@ -604,6 +731,7 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       int ord = tuning().sync_order;
       if (shape >= 0) ord = shape_sync_order(shape);
       if (ord < 0) ord = (K == 1 && C == 1) ? (far ? 2 : 1) : (K == 2 && C == 2 && !far) ? 1 : 0;
+      if (ord > 2) ord = 2;  // a stride of 4 groups is for the pair layout's 8 KiB tiles
       int ilv = tuning().sync_interleave;
       // quarters need the row-run patch order (a step's patches then cover
       // whole rows of the tile)
@@ -618,8 +746,8 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       int r = g.F - g.s - (JU == 4 ? 2 : JU == 2 ? 1 : 0);
       if (ord == 0 || r > rmax) r = rmax;
       if (r < 0) r = 0;
-      const int par = ord == 2 ? 1 : 0;
-      uint64_t wg = sync_units(g.ngroups, sl, (uint32_t)sw, r, par);
+      const int ps = ord == 2 ? 1 : 0;
+      uint64_t wg = sync_units(g.ngroups, sl, (uint32_t)sw, r, ps);
       // grid: the quarter orders at 3/4 of a workgroup per CU (measured
       // 1-4 % faster than one per CU at most tile bits)
       uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
@@ -629,10 +757,10 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       if (wg > wcap) wg = wcap;
       const dim3 grid((unsigned)wg), block((unsigned)(64 * sw));
       switch (smode) {
-        case 1: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 1>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
-        case 2: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 2>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
-        case 3: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 3>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par); break;
-        default: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 0>), grid, block, 0, s, hp, gs, cf, coef_dev, r, par);
+        case 1: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 1>), grid, block, 0, s, hp, gs, cf, coef_dev, r, ps); break;
+        case 2: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 2>), grid, block, 0, s, hp, gs, cf, coef_dev, r, ps); break;
+        case 3: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 3>), grid, block, 0, s, hp, gs, cf, coef_dev, r, ps); break;
+        default: hipLaunchKernelGGL((conj_sync_kernel<T, K, C, FORM, 0>), grid, block, 0, s, hp, gs, cf, coef_dev, r, ps);
       }
       return hipGetLastError();
     }

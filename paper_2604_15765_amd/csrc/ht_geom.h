@@ -173,25 +173,25 @@ HT_HD void lane_block(uint32_t b, int F, int s, bool ilv, uint32_t& pidx, uint32
   }
 }
 
-// Items of one step of a workgroup of wpb waves (conj_sync_kernel), for
-// groups of 2^sl steps: 2^r consecutive steps of each of
-// wpb / 2^r groups (r <= sl, 2^r <= wpb), the groups consecutive or, with
-// par, every other one of twice as many (the other half in the next unit).
-// r = min(sl, log2 wpb), par = 0 takes whole groups; r = 0 gives every wave
+// Items of one step of a workgroup of wpb waves (the step kernels), for
+// groups of 2^sl steps: 2^r consecutive steps of each of wpb / 2^r groups
+// (r <= sl, 2^r <= wpb), the groups consecutive (ps = 0) or every 2^ps-th
+// of 2^ps times as many (the others in the next 2^ps - 1 units).
+// r = min(sl, log2 wpb), ps = 0 takes whole groups; r = 0 gives every wave
 // the same patches of its own group's tiles.  Every choice is a bijection
 // of (unit, wave) onto (group, step), so results do not depend on it.
-HT_HD uint64_t sync_units(uint64_t ngroups, int sl, uint32_t wpb, int r, int par) {
-  const uint64_t span = (uint64_t)(wpb >> r) << par;  // groups one unit spans
-  return ((ngroups + span - 1) / span) << (sl - r + par);
+HT_HD uint64_t sync_units(uint64_t ngroups, int sl, uint32_t wpb, int r, int ps) {
+  const uint64_t span = (uint64_t)(wpb >> r) << ps;  // groups one unit spans
+  return ((ngroups + span - 1) / span) << (sl - r + ps);
 }
 
-HT_HD void sync_item(uint64_t u, uint32_t wib, uint32_t wpb, int sl, int r, int par, uint64_t& grp,
+HT_HD void sync_item(uint64_t u, uint32_t wib, uint32_t wpb, int sl, int r, int ps, uint64_t& grp,
                      uint32_t& step) {
   const int sr = sl - r;
-  const uint64_t blk = u >> (sr + par);
-  const uint64_t h = par ? (u >> sr) & 1u : 0u;
+  const uint64_t blk = u >> (sr + ps);
+  const uint64_t h = (u >> sr) & ((1ull << ps) - 1u);
   const uint32_t sb = (uint32_t)u & ((1u << sr) - 1u);
-  grp = blk * ((uint64_t)(wpb >> r) << par) + ((uint64_t)(wib >> r) << par) + h;
+  grp = blk * ((uint64_t)(wpb >> r) << ps) + ((uint64_t)(wib >> r) << ps) + h;
   step = (sb << r) | (wib & ((1u << r) - 1u));
 }
 

@@ -93,6 +93,49 @@ void run(const CheckedMem& mem, int n, int m, const ht::PreparedOp& op, int orde
   constexpr int JP = K == 1 ? 2 : 1;
   bool use_pairs = false;
   if constexpr (K == 1 || (K == 2 && FORM == 0)) use_pairs = pairs && g.F >= 4 && (K == C || g.ipos[0] != 0);
+  if constexpr (K == 1 || (K == 2 && FORM == 0)) {
+    if (use_pairs && order >= 2) {
+      // the pair step kernel's split of the work (order 2..5: item order
+      // 0..3): every (unit, wave) item of sync_item that is not past the end
+      // and not a diagonal group, its pairs loaded and updated by every
+      // lane; then, with a tile-selecting target, the diagonal groups in the
+      // block layout (pair_diag_kernel)
+      constexpr int LW = K == 1 ? 4 : 3;
+      constexpr uint32_t WPB = 1u << LW;
+      int sl, r, ps;
+      ht::pair_sync_order(g.F, JP, LW, order - 2, sl, r, ps);
+      const uint64_t nu = ht::sync_units(g.ngroups, sl, WPB, r, ps);
+      for (uint64_t u = 0; u < nu; ++u)
+        for (uint32_t w = 0; w < WPB; ++w) {
+          uint64_t grp;
+          uint32_t step;
+          ht::sync_item(u, w, WPB, sl, r, ps, grp, step);
+          if (grp >= g.ngroups) continue;
+          ht::GroupCtx<C> gc;
+          ht::group_ctx<K, C>(grp, g, gc);
+          if (gc.diag) continue;
+          for (uint32_t lane = 0; lane < 64; ++lane) {
+            ht::PairStep<JP, K, CheckedMem> st;
+            ht::pair_load<JP, K, C>(mem, g, gc, lane, step * JP, st);
+            ht::pair_update_store<JP, K, C, FORM>(mem, g, gc, cf, st);
+            ++*lanes_run;
+          }
+        }
+      if (C > 0) {
+        const uint64_t nts = ht::grid_rows(g.ngroups);
+        for (uint64_t ti = 0; ti < nts; ++ti) {
+          ht::GroupCtx<C> gc;
+          ht::group_ctx<K, C>(ht::diag_group(ti), g, gc);
+          if (!gc.diag) continue;
+          for (uint32_t lane = 0; lane < 64; ++lane) {
+            ht::conj_group_lane<JU, K, C, FORM>(mem, g, gc, cf, lane);
+            ++*lanes_run;
+          }
+        }
+      }
+      return;
+    }
+  }
   for (uint64_t grp = 0; grp < g.ngroups; ++grp) {
     ht::GroupCtx<C> gc;
     ht::group_ctx<K, C>(grp, g, gc);
@@ -197,7 +240,8 @@ extern "C" {
 // raw: host c128 tiled storage of nelems entries (2*nelems doubles), updated
 // in place.  write_counts / read_counts: nelems int32 each, zeroed by the
 // caller, or NULL.  order: 0 = whole groups per lane, 1 = the per-step job
-// ranges of the flattened work order.  ilv: the alternating
+// ranges of the flattened work order; with pairs, 2..5 = the pair step
+// kernel's split of the work in item order 0..3.  ilv: the alternating
 // patch order (lane_block).  pairs: the pair layout of complex64
 // passes (ht_pair.h) wherever it applies, checked on this complex128 copy.  native: allow the
 // native pass for permutation-and-phase operations; *form (if not NULL)
@@ -259,12 +303,12 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
 // u < sync_units(...) and wave w < wpb, grp[u * wpb + w] and step[...] as
 // sync_item gives them.  Returns the number of units, or 0 when they exceed
 // max_units.
-uint64_t htc_sync_items(uint64_t ngroups, int sl, uint32_t wpb, int r, int par, uint64_t max_units,
+uint64_t htc_sync_items(uint64_t ngroups, int sl, uint32_t wpb, int r, int ps, uint64_t max_units,
                         uint64_t* grp, uint32_t* step) {
-  const uint64_t nu = ht::sync_units(ngroups, sl, wpb, r, par);
+  const uint64_t nu = ht::sync_units(ngroups, sl, wpb, r, ps);
   if (nu > max_units) return 0;
   for (uint64_t u = 0; u < nu; ++u)
-    for (uint32_t w = 0; w < wpb; ++w) ht::sync_item(u, w, wpb, sl, r, par, grp[u * wpb + w], step[u * wpb + w]);
+    for (uint32_t w = 0; w < wpb; ++w) ht::sync_item(u, w, wpb, sl, r, ps, grp[u * wpb + w], step[u * wpb + w]);
   return nu;
 }
 

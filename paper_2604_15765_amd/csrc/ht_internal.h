@@ -46,7 +46,8 @@ struct LaunchTuning {
   int sync_wg_per_cu = 1;   // workgroups per CU of the synchronised pass
   int sync_order = -1;      // items of a synchronised workgroup step: -1 automatic, 0 whole
                             // groups, 1 one quarter of every tile of consecutive groups,
-                            // 2 the same of every other group
+                            // 2 the same of every other group, 3 of every fourth (pair layout;
+                            // the block layout takes 2 for it)
   int sync_interleave = -1; // patch order of the synchronised pass: -1 automatic (0 for two
                             // tile-selecting targets, else as "interleave"), 0 or 1
   int pipe_waves = 0;       // steps with the next one prefetched: 0 off, 4 or 8 waves per workgroup
@@ -67,20 +68,25 @@ enum PassShape {
   kShapeSyncQ = 7,     //   ... quarters of consecutive groups (7..9)
   kShapeSyncQA = 10,   //   ... quarters of every other group (10..12)
   kShapeStageA = 13,   // LDS-staged pass, every other 16 KiB granule per step (13..15)
-  kShapeCount = 16
+  kShapeSyncQ4 = 16,   // 16-wave steps, quarters of every fourth group (16..18; complex64
+                       // pair layout, the block layout takes every other group)
+  kShapeCount = 19
 };
 inline bool shape_is_stage(int shape) {
-  return (shape >= kShapeStage && shape < kShapeSync) || (shape >= kShapeStageA && shape < kShapeCount);
+  return (shape >= kShapeStage && shape < kShapeSync) || (shape >= kShapeStageA && shape < kShapeSyncQ4);
 }
-inline bool shape_is_sync(int shape) { return shape >= kShapeSync && shape < kShapeStageA; }
-// Item order of a step shape: 0 whole groups, 1 quarters, 2 quarters of every other group.
-inline int shape_sync_order(int shape) { return (shape - kShapeSync) / 3; }
+inline bool shape_is_sync(int shape) {
+  return (shape >= kShapeSync && shape < kShapeStageA) || (shape >= kShapeSyncQ4 && shape < kShapeCount);
+}
+// Item order of a step shape: 0 whole groups, 1 quarters, 2 quarters of
+// every other group, 3 of every fourth.
+inline int shape_sync_order(int shape) { return shape >= kShapeSyncQ4 ? 3 : (shape - kShapeSync) / 3; }
 // Step order of a staged shape: 0 contiguous, 1 every other 16 KiB granule.
 inline int shape_stage_order(int shape) { return shape >= kShapeStageA ? 1 : 0; }
 // Grid of a shape: workgroups for num_cu compute units.
 inline uint64_t shape_grid(int shape, int num_cu) {
   const int i = shape_is_stage(shape) ? (shape - (shape >= kShapeStageA ? kShapeStageA : kShapeStage))
-                : shape_is_sync(shape) ? (shape - kShapeSync) % 3
+                : shape_is_sync(shape) ? (shape - (shape >= kShapeSyncQ4 ? kShapeSyncQ4 : kShapeSync)) % 3
                                        : 0;
   const int f = i == 1 ? 6 : i == 2 ? 5 : 8;
   return (uint64_t)num_cu * (uint64_t)f / 8u;

@@ -149,7 +149,8 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
     const bool skip_stage = h->dtype == HT_C64 && tc.k == 2 && tc.form == 1;  // measured 7x slower staged
     std::vector<int> cands = {ht::kShapeLane};
     for (int sh = 1; sh < ht::kShapeCount; ++sh)
-      if ((tc.c == 0 && !skip_stage && ht::shape_is_stage(sh)) || (tc.c > 0 && ht::shape_is_sync(sh)))
+      if ((tc.c == 0 && !skip_stage && ht::shape_is_stage(sh)) ||
+          (tc.c > 0 && ht::shape_is_sync(sh) && (h->dtype == HT_C64 || ht::shape_sync_order(sh) < 3)))
         cands.push_back(sh);
     double best = 1e300, lane_ms = 0.0;
     int best_shape = ht::kShapeLane;

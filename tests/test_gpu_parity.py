@@ -196,6 +196,11 @@ STEP_TUNINGS = [
     {"sync_waves": 16, "sync_order": 2},
     {"sync_waves": 8, "sync_order": 2},
     {"sync_waves": 4, "sync_order": 1, "sync_interleave": 1},
+    # complex64: the pair layout in workgroup steps (every group, every
+    # fourth), and the block layout in steps
+    {"sync_waves": 16, "sync_order": 3},
+    {"sync_waves": 8, "sync_order": 3, "pair_jp2": 0},
+    {"sync_waves": 16, "sync_order": 1, "pairs": 0},
     # complex64 pair passes with two tile-selecting targets in plain mode: one pair per step
     {"pair_jp2": 0},
     # steps with the next one prefetched, with and without the barrier
@@ -204,7 +209,7 @@ STEP_TUNINGS = [
     {"pipe_waves": 8},
 ]
 STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
-                 "sync_order": -1, "stage_order": -1,
+                 "sync_order": -1, "stage_order": -1, "pairs": 1,
                  "pipe_waves": 0, "pipe_barrier": 1, "native": 1, "pair_jp2": 1}
 
 

@@ -323,6 +323,34 @@ def test_pair_layout_two_qubit_ops(hc, m):
             assert np.array_equal(p, q), (n, m, a, b)
 
 
+@pytest.mark.parametrize("m", [4, 5])
+def test_pair_step_kernel_split_covers_every_entry_once(hc, m):
+    """The pair layout in workgroup-wide steps (pair_sync_kernel): the work
+    split of its four item orders -- sync_item's (unit, wave) items minus
+    the diagonal groups, then the diagonal groups in the block layout when a
+    target selects tiles (pair_diag_kernel) -- writes every stored entry
+    exactly once and gives bitwise the block layout's result, for one-qubit
+    ops at every position (unitaries and channels, both pictures) and
+    two-qubit unitaries on a sample of ordered pairs, intra and
+    tile-selecting."""
+    rng = synth.make_rng(1450 + m)
+    for n in (m + 1, m + 3):
+        H = synth.random_hermitian_dense(n, rng)
+        raw = layout.encode(H, m)
+        cases = [([a], synth.haar_unitary(2, rng)[None]) for a in range(1, n)]
+        cases += [([a], synth.random_kraus_set(1, 3, rng)) for a in range(1, n, 2)]
+        pairs = [(a, b) for a in range(n) for b in range(n) if a != b]
+        for i in rng.choice(len(pairs), 8, replace=False):
+            cases.append((list(pairs[i]), synth.haar_unitary(4, rng)[None]))
+        for targets, kraus in cases:
+            heis = bool(rng.integers(2))
+            want, _ = emulate(hc, raw, n, m, targets, kraus, heis, 0, pairs=0)
+            for order in (2, 3, 4, 5):
+                got, wc = emulate(hc, raw, n, m, targets, kraus, heis, order, pairs=1)
+                assert np.all(wc == 1), (n, m, targets, order, np.unique(wc))
+                assert np.array_equal(got, want), (n, m, targets, order)
+
+
 # ----------------------------------------------- k = 3 Kraus form (form 3)
 
 def check_k3(f, n, m, targets, kraus, heis, rng, native=0):
@@ -363,12 +391,12 @@ def test_k3_kraus_form_full_rank_and_permutations(hc):
 
 
 def test_step_kernel_item_orders_cover_every_item_once():
-    """The workgroup-wide step kernel's item orders (sync_item): for every
+    """The workgroup-wide step kernels' item orders (sync_item): for every
     group count, steps per group, waves per workgroup, steps per group in
-    one workgroup step (r) and every-other-group choice, the (unit, wave)
+    one workgroup step (r) and group stride (1, 2 or 4), the (unit, wave)
     pairs reach each (group, step) of the pass exactly once, every step
-    index is in range, and whole groups (r = min(sl, log2 waves), no
-    alternation) are the consecutive items u * waves + w."""
+    index is in range, and whole groups (r = min(sl, log2 waves), stride 1)
+    are the consecutive items u * waves + w."""
     if not os.path.exists(SO):
         pytest.skip("_hostcheck.so not built")
     f = ctypes.CDLL(SO).htc_sync_items
@@ -381,18 +409,18 @@ def test_step_kernel_item_orders_cover_every_item_once():
             for lw in (2, 3, 4):
                 wpb = 1 << lw
                 for r in range(min(sl, lw) + 1):
-                    for par in (0, 1):
+                    for ps in (0, 1, 2):
                         grp = np.zeros(cap * wpb, dtype=np.uint64)
                         step = np.zeros(cap * wpb, dtype=np.uint32)
-                        nu = f(ng, sl, wpb, r, par, cap, grp.ctypes.data, step.ctypes.data)
+                        nu = f(ng, sl, wpb, r, ps, cap, grp.ctypes.data, step.ctypes.data)
                         assert 0 < nu <= cap
                         g, s = grp[:nu * wpb], step[:nu * wpb]
                         assert np.all(s < (1 << sl))
                         live = g < ng
                         key = g[live] * (1 << sl) + s[live]
                         assert np.array_equal(np.sort(key), np.arange(ng << sl, dtype=np.uint64)), \
-                            (ng, sl, wpb, r, par)
-                        if r == min(sl, lw) and par == 0:
+                            (ng, sl, wpb, r, ps)
+                        if r == min(sl, lw) and ps == 0:
                             it = np.arange(nu * wpb, dtype=np.uint64)
                             assert np.array_equal(g, it >> np.uint64(sl))
                             assert np.array_equal(s, (it & np.uint64((1 << sl) - 1)).astype(np.uint32))
