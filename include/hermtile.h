@@ -585,8 +585,9 @@ ht_status ht_set_tuning(const char* name, int64_t value);
  * of whole groups at the same grids, 7-9 steps of one quarter of every tile
  * of 16 groups, 10-12 the same of every other group of 32, 13-15 staged
  * with every other 16 KiB granule per step, 16-18 steps of every fourth
- * group, complex64 only), its ms per pass, the lane-patch kernel's ms per
- * pass;
+ * group, complex64 only, 19 staged with alternate granules in 64 KiB steps
+ * of two 256-thread workgroups per CU), its ms per pass, the lane-patch
+ * kernel's ms per pass;
  * nrows (may be NULL): classes tuned.  HT_EINVAL for a NULL handle, reps
  * outside [1, 16] or rows NULL with max_rows > 0.  Call it while no other
  * thread enqueues passes (it switches the process-wide launch tuning). */

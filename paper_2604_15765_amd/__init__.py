@@ -225,7 +225,8 @@ PASS_SHAPES = ("lane", "stage", "stage_3/4", "stage_5/8", "steps", "steps_3/4", 
                "steps_quarter", "steps_quarter_3/4", "steps_quarter_5/8",
                "steps_quarter_alt", "steps_quarter_alt_3/4", "steps_quarter_alt_5/8",
                "stage_alt", "stage_alt_3/4", "stage_alt_5/8",
-               "steps_quarter_4th", "steps_quarter_4th_3/4", "steps_quarter_4th_5/8")
+               "steps_quarter_4th", "steps_quarter_4th_3/4", "steps_quarter_4th_5/8",
+               "stage_alt_256x2")
 
 
 def set_pass_shape(dtype: str, n: int, tile_log2: int, row: dict) -> None:

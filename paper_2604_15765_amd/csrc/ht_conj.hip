@@ -645,12 +645,19 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       stage = large && !(sizeof(T) == 4 && K == 2 && FORM == 1) ? 1 : 0;
     }
     if (shape >= 0) stage = shape_is_stage(shape) ? 1 : 0;
-    const int sth = tuning().stage_threads;
+    // The two-qubit transfer form (a 16 x 16 matrix per block) in 64 KiB
+    // steps of two 256-thread workgroups per CU, so that one computes while
+    // the other loads: measured 12.3 ms per n = 16 c128 pass against
+    // 12.9-13.1 for one 512-thread workgroup per CU.
+    const bool auto_shape = shape < 0 && tuning().stage < 0;
+    const bool two_wg = (shape >= 0 && shape == kShapeStage2) || (auto_shape && K == 2 && FORM == 1);
+    const int sth = two_wg ? 256 : shape >= 0 ? shape_stage_threads(shape) : tuning().stage_threads;
     const uint64_t step_bytes = 16ull * kStageVecs * (uint64_t)sth;
     if (stage == 1 && tile_bytes <= step_bytes) {
       const uint64_t steps_total = (nent * 2 * sizeof(T) + step_bytes - 1) / step_bytes;
       uint64_t sw = tuning().stage_grid > 0 ? (uint64_t)tuning().stage_grid
                                             : (uint64_t)num_cu * (uint64_t)tuning().stage_wg_per_cu;
+      if (two_wg && auto_shape) sw = 2u * (uint64_t)num_cu;
       if (shape >= 0) sw = shape_grid(shape, num_cu);
       if (sw > steps_total) sw = steps_total;
       const bool pipe = tuning().stage_pipe != 0;

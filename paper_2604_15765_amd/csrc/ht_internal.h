@@ -70,21 +70,27 @@ enum PassShape {
   kShapeStageA = 13,   // LDS-staged pass, every other 16 KiB granule per step (13..15)
   kShapeSyncQ4 = 16,   // 16-wave steps, quarters of every fourth group (16..18; complex64
                        // pair layout, the block layout takes every other group)
-  kShapeCount = 19
+  kShapeStage2 = 19,   // LDS-staged pass, alternate granules, 64 KiB steps of 256-thread
+                       // workgroups, two per CU
+  kShapeCount = 20
 };
 inline bool shape_is_stage(int shape) {
-  return (shape >= kShapeStage && shape < kShapeSync) || (shape >= kShapeStageA && shape < kShapeSyncQ4);
+  return (shape >= kShapeStage && shape < kShapeSync) || (shape >= kShapeStageA && shape < kShapeSyncQ4) ||
+         shape == kShapeStage2;
 }
 inline bool shape_is_sync(int shape) {
-  return (shape >= kShapeSync && shape < kShapeStageA) || (shape >= kShapeSyncQ4 && shape < kShapeCount);
+  return (shape >= kShapeSync && shape < kShapeStageA) || (shape >= kShapeSyncQ4 && shape < kShapeStage2);
 }
 // Item order of a step shape: 0 whole groups, 1 quarters, 2 quarters of
 // every other group, 3 of every fourth.
 inline int shape_sync_order(int shape) { return shape >= kShapeSyncQ4 ? 3 : (shape - kShapeSync) / 3; }
 // Step order of a staged shape: 0 contiguous, 1 every other 16 KiB granule.
 inline int shape_stage_order(int shape) { return shape >= kShapeStageA ? 1 : 0; }
+// Threads per workgroup of a staged shape.
+inline int shape_stage_threads(int shape) { return shape == kShapeStage2 ? 256 : 512; }
 // Grid of a shape: workgroups for num_cu compute units.
 inline uint64_t shape_grid(int shape, int num_cu) {
+  if (shape == kShapeStage2) return 2u * (uint64_t)num_cu;
   const int i = shape_is_stage(shape) ? (shape - (shape >= kShapeStageA ? kShapeStageA : kShapeStage))
                 : shape_is_sync(shape) ? (shape - (shape >= kShapeSyncQ4 ? kShapeSyncQ4 : kShapeSync)) % 3
                                        : 0;

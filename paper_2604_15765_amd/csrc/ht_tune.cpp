@@ -160,6 +160,7 @@ extern "C" ht_status ht_tune_passes(ht_herm* h, int reps, int max_rows, double* 
       ht::tuning().stage = ht::shape_is_stage(shape) ? 1 : 0;
       ht::tuning().stage_grid = ht::tuning().stage ? (int)ht::shape_grid(shape, h->num_cu) : 0;
       ht::tuning().stage_order = ht::tuning().stage ? ht::shape_stage_order(shape) : -1;
+      ht::tuning().stage_threads = ht::tuning().stage ? ht::shape_stage_threads(shape) : saved.stage_threads;
       ht::tuning().sync_waves = ht::shape_is_sync(shape) ? 16 : 0;
       ht::tuning().sync_grid = ht::tuning().sync_waves ? (int)ht::shape_grid(shape, h->num_cu) : 0;
       ht::tuning().sync_order = ht::tuning().sync_waves ? ht::shape_sync_order(shape) : -1;

@@ -234,7 +234,7 @@ def test_pass_shape_arguments(ht):
     ok = [(C128, 16, 5, 1, 0, 0, 1, 0, 1), (C128, 16, 5, 1, 1, 1, 0, 0, 5), (C64, 16, 5, 2, 2, 0, 0, 1, 6),
           (C128, 16, 5, 2, 1, 0, 1, 0, 0), (C128, 16, 5, 1, 0, 0, 0, 0, -1), (C64, 9, 3, 2, 0, 1, 1, 0, 3),
           (C128, 16, 5, 1, 1, 0, 0, 1, 12), (C128, 9, 3, 2, 2, 1, 0, 1, 8), (C128, 8, 3, 1, 1, 0, 0, 0, 10),
-          (C64, 16, 5, 1, 0, 1, 0, 0, 14), (C64, 16, 5, 1, 1, 1, 0, 1, 16)]
+          (C64, 16, 5, 1, 0, 1, 0, 0, 14), (C64, 16, 5, 1, 1, 1, 0, 1, 16), (C128, 16, 5, 2, 0, 1, 1, 0, 19)]
     bad = [(2, 16, 5, 1, 0, 0, 0, 0, 0),    # unknown dtype
            (C128, 0, 5, 1, 0, 0, 0, 0, 0),  # n out of range
            (C128, 16, 9, 1, 0, 0, 0, 0, 0),  # tile_log2 out of range
@@ -250,7 +250,8 @@ def test_pass_shape_arguments(ht):
            (C128, 16, 5, 1, 0, 0, 0, 0, 4),  # step shape without one
            (C128, 16, 5, 1, 1, 0, 0, 0, 15),  # staged (alternate granules) with a tile-selecting target
            (C128, 16, 5, 1, 0, 0, 0, 0, 17),  # step shape (every fourth group) without a tile-selecting target
-           (C128, 16, 5, 1, 0, 0, 0, 0, 19)]  # unknown shape
+           (C128, 16, 5, 1, 1, 0, 0, 0, 19),  # staged shape with a tile-selecting target
+           (C128, 16, 5, 1, 0, 0, 0, 0, 20)]  # unknown shape
     try:
         for args in ok:
             assert f(*args) == 0, (args, ht.lib.ht_last_error())
