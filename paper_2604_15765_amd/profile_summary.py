@@ -56,8 +56,10 @@ def kernel_class(name: str):
     with the granule-order flag, 'stage_kernel<double, 2, 1, 512, true, true>'),
     'native_kernel<float, 3, 2, 0, 16, 0>' -> 'c64_k3_c2_native',
     'k3_kernel<double, 1, 3>' -> 'c128_k3_c1_kraus',
-    'pair_kernel<1, 1, 0, 3, 2>' -> 'c64_k1_c1_direct' (complex64 only); None
-    otherwise."""
+    'pair_kernel<1, 1, 0, 3, 2>' -> 'c64_k1_c1_direct' (complex64 only; also
+    the step form 'pair_sync_kernel<1, 1, 0, 3, 2, 1024>'), and the pair
+    passes' diagonal-group launch 'pair_diag_kernel<2, 2, 0, 3>' ->
+    'c64_k2_c2_direct_diag'; None otherwise."""
     m = re.search(r"conj_(?:sync_|pipe_)?kernel<(double|float), (\d), (\d), (\d), (\d)", name)
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
@@ -74,9 +76,12 @@ def kernel_class(name: str):
     if m:
         dt = "c128" if m.group(1) == "double" else "c64"
         return f"{dt}_k3_c{m.group(2)}_kraus"
-    m = re.search(r"pair_kernel<(\d), (\d), (\d), (\d), (\d)>", name)
+    m = re.search(r"pair_(?:sync_)?kernel<(\d), (\d), (\d), (\d), (\d)(?:, \d+)?>", name)
     if m:
         return f"c64_k{m.group(1)}_c{m.group(2)}_{'direct' if m.group(3) == '0' else 'transfer'}"
+    m = re.search(r"pair_diag_kernel<(\d), (\d), (\d), (\d)>", name)
+    if m:
+        return f"c64_k{m.group(1)}_c{m.group(2)}_{'direct' if m.group(3) == '0' else 'transfer'}_diag"
     return None
 
 

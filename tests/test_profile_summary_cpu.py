@@ -19,6 +19,9 @@ def test_kernel_class():
         "ht::stage_kernel<double, 1, 0, 512, true>": "c128_k1_c0_direct",
         "ht::stage_kernel<float, 2, 1, 256, false>": "c64_k2_c0_transfer",
         "ht::stage_kernel<double, 1, 1, 512, true, true>": "c128_k1_c0_transfer",
+        "ht::pair_sync_kernel<1, 1, 1, 3, 2, 1024>": "c64_k1_c1_transfer",
+        "ht::pair_sync_kernel<2, 2, 0, 0, 1, 512>": "c64_k2_c2_direct",
+        "ht::pair_diag_kernel<2, 2, 0, 3>": "c64_k2_c2_direct_diag",
         "ht::stage_kernel<float, 2, 0, 512, false, true>": "c64_k2_c0_direct",
         "ht::trace_partial_kernel<double>": None,
         "ht::batch_kernel<float>": None,
