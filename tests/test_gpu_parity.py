@@ -188,6 +188,7 @@ STEP_TUNINGS = [
     # ... every other 16 KiB granule per step
     {"stage": 1, "stage_threads": 512, "stage_pipe": 1, "stage_order": 1},
     {"stage": 1, "stage_threads": 256, "stage_pipe": 0, "stage_order": 1},
+    {"stage": 1, "stage_threads": 256, "stage_pipe": 1, "stage_order": 1, "stage_grid": 8},
     # workgroup-wide steps, both patch orders, the three item orders
     {"sync_waves": 16, "sync_order": 0},
     {"sync_waves": 8, "sync_interleave": 0, "sync_order": 0},
@@ -209,7 +210,7 @@ STEP_TUNINGS = [
     {"pipe_waves": 8},
 ]
 STEP_DEFAULTS = {"stage": -1, "stage_threads": 512, "stage_pipe": 1, "sync_waves": -1, "sync_interleave": -1,
-                 "sync_order": -1, "stage_order": -1, "pairs": 1,
+                 "sync_order": -1, "stage_order": -1, "pairs": 1, "stage_grid": 0,
                  "pipe_waves": 0, "pipe_barrier": 1, "native": 1, "pair_jp2": 1}
 
 
@@ -264,6 +265,52 @@ def test_step_kernels_give_bitwise_equal_results(ht, dtype):
     finally:
         for k, v in STEP_DEFAULTS.items():
             ht.set_tuning(k, v)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_every_pass_shape_gives_bitwise_equal_results(ht, dtype):
+    """Every launch shape the pass tuner can choose (ht_set_pass_shape,
+    shapes 0-19: lane patches, staged steps in both orders, grids and
+    workgroup sizes, workgroup steps in every item order and grid), set for
+    every pass class it applies to, gives bitwise the lane-patch kernel's
+    result on a sequence of one- and two-qubit unitaries and channels, at
+    tile edges 8 (tile bits up to 5, both buckets of the highest
+    tile-selecting target) and 32 (the complex64 pair layout applies)."""
+    rng = synth.make_rng(473)
+    n = 9
+    H = synth.random_hermitian_dense(n, rng)
+    ops = []
+    for _ in range(24):
+        k = int(rng.integers(1, 3))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        ops.append((t, synth.haar_unitary(1 << k, rng)[None] if rng.random() < 0.5
+                    else synth.random_kraus_set(k, 2, rng)))
+    f = ht.lib.ht_set_pass_shape
+    dt = {"c128": 0, "c64": 1}[dtype]
+    classes = [(k, c, form, low, far) for k in (1, 2) for c in range(k + 1) for form in (0, 1)
+               for low in (0, 1) for far in (0, 1)]
+
+    def run(m):
+        g = make(ht, n, m, H, dtype)
+        for t, mats in ops:
+            g.apply_channel(t, mats)
+        raw = g.raw_entries()
+        g.close()
+        return raw
+
+    for m in (3, 5):
+        try:
+            base = run(m)  # no tuned shapes: the automatic choice
+            for shape in range(len(ht.PASS_SHAPES)):
+                applied = [cl for cl in classes if f(dt, n, m, *cl, shape) == 0]
+                assert applied or shape == 0, (m, shape)
+                raw = run(m)
+                assert np.array_equal(base, raw), (dtype, m, ht.PASS_SHAPES[shape])
+                for cl in applied:
+                    f(dt, n, m, *cl, -1)
+        finally:
+            for cl in classes:
+                f(dt, n, m, *cl, -1)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
