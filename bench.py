@@ -138,6 +138,27 @@ def cpu_baseline(n_full: int, seed: int) -> dict:
     }
 
 
+def copy_ceiling(ht, h, reps: int = 5) -> dict:
+    """The library's copy kernel over a second buffer of h's size: read
+    plus write bytes per second, the practical streaming ceiling that the
+    pass's in-place read-modify-write compares with."""
+    import torch
+    b = ht.Herm(h.n, h.tile_log2, h.dtype)
+    try:
+        b.copy_from(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.copy_from(h)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        b.close()
+    gbps = 2 * h.nbytes / dt / 1e9
+    return {"GBps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS, "bytes_per_launch": 2 * h.nbytes,
+            "note": "out-of-place copy of an operator-sized buffer, host-timed over 5 launches"}
+
+
 def c64_run(ht, G, layers, args, codes, coeffs, tr_c128, ev_c128, h128) -> dict:
     """The same steps from the same initial state in complex64 storage (FP64
     arithmetic and reductions, the pair layout where it applies): its own
@@ -622,6 +643,7 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": dom_avg_ms,
             "bytes_per_launch": per_op_bytes,
+            "copy_kernel": copy_ceiling(ht, h),
         },
         "kernel_classes": classes,
         "final_trace": tr,
