@@ -716,10 +716,16 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   {
     // workgroup-wide steps
     int sw = tuning().sync_waves;
-    // complex64 of 1 GiB and more: one-qubit passes with a tile-selecting
-    // target in the pair layout's steps (pair_sync_kernel)
+    // complex64 of 1 GiB and more: passes with a tile-selecting target and
+    // no intra target below bit 3 in the pair layout's steps
+    // (pair_sync_kernel; k = 2 direct form only, as the pair layout).
+    // Measured at n = 16 against pair_kernel: k = 1 5.0-5.3 -> 5.8-5.9
+    // TB/s at tile bits 0-5; k = 2 whole groups 5.09-5.12 -> 5.15-5.35 at
+    // low tile bits, equal at the top ones, and the mirrored tiles'
+    // half-line excess (+2.7 % traffic) gone; an intra target below bit 3
+    // ran 3.2 TB/s in steps and stays on pair_kernel.
     const bool big64 = sizeof(T) == 4 && nent * 2 * sizeof(T) >= (1ull << 30);
-    const bool pairs64 = big64 && K == 1 && C == 1 && g.F >= 4 && tuning().pairs != 0;
+    const bool pairs64 = big64 && C > 0 && (K == 1 || FORM == 0) && low >= 3 && g.F >= 4 && tuning().pairs != 0;
     if (sw < 0) sw = ((big && C > 0 && low >= 3 && !(K == 2 && C == 1)) || pairs64) ? 16 : 0;
     if (shape >= 0) sw = (C > 0 && shape_is_sync(shape)) ? 16 : 0;
     if (sw > 0) {
