@@ -623,8 +623,8 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
   // lane-patch kernel 4.7-5.7); complex128 passes with a tile-selecting
   // target in workgroup-wide steps of 16 waves whose item order follows the
   // target's tile bit (5.45-5.87, whole groups 5.2-5.5); an intra target
-  // below bit 3 beside a tile-selecting one, and one intra beside one
-  // tile-selecting target, stay on the lane-patch kernel.
+  // below bit 3 beside a tile-selecting one stays on the lane-patch kernel;
+  // complex64 with a tile-selecting target takes the pair step kernel.
   constexpr int KI = K - C;
   const int low = KI > 0 ? g.ipos[0] : 99;
   // highest tile-selecting target at tile bit 4 or above
@@ -726,7 +726,11 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
     // ran 3.2 TB/s in steps and stays on pair_kernel.
     const bool big64 = sizeof(T) == 4 && nent * 2 * sizeof(T) >= (1ull << 30);
     const bool pairs64 = big64 && C > 0 && (K == 1 || FORM == 0) && low >= 3 && g.F >= 4 && tuning().pairs != 0;
-    if (sw < 0) sw = ((big && C > 0 && low >= 3 && !(K == 2 && C == 1)) || pairs64) ? 16 : 0;
+    // complex128: every pass with a tile-selecting target and no intra
+    // target below bit 3 (k = 2 with one intra target: the quarter order
+    // measured 12.3 ms at targets (4, 5) against 13.2-13.6 for the
+    // lane-patch kernel, though its 16-wave form spills two registers)
+    if (sw < 0) sw = ((big && C > 0 && low >= 3) || pairs64) ? 16 : 0;
     if (shape >= 0) sw = (C > 0 && shape_is_sync(shape)) ? 16 : 0;
     if (sw > 0) {
       // complex64 where the pair layout applies: the pair step kernel
@@ -743,7 +747,7 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& op, const 
       // 5.30 -> 5.44 (quarters), (4, 5) 5.26 -> 5.20, (9, 10) 5.08 -> 4.90.
       int ord = tuning().sync_order;
       if (shape >= 0) ord = shape_sync_order(shape);
-      if (ord < 0) ord = (K == 1 && C == 1) ? (far ? 2 : 1) : (K == 2 && C == 2 && !far) ? 1 : 0;
+      if (ord < 0) ord = C == 1 ? (far ? 2 : 1) : (K == 2 && C == 2 && !far) ? 1 : 0;
       if (ord > 2) ord = 2;  // a stride of 4 groups is for the pair layout's 8 KiB tiles
       int ilv = tuning().sync_interleave;
       // quarters need the row-run patch order (a step's patches then cover
