@@ -158,54 +158,76 @@ HT_HD void native3_group_lane(const Mem& mem, const ConjGeom<3, C>& g, const Nat
   }
 }
 
-// All blocks one lane owns in the current group: loads of every changing
-// entry of JU blocks first (from their permuted sources), then the products
-// with the coefficients, written to the entries themselves.  The sources of
-// a block's entries lie in the same block, and blocks are disjoint.
+// JU blocks of a lane: base rows and columns, whether each is the lane's,
+// and the loaded sources of its changing entries.
+template <int JU, int K>
+struct NativeStep {
+  uint32_t bp[JU], bq[JU];
+  bool on[JU];
+  cd x[JU][(1 << K) * (1 << K)];
+};
+
+// Load every changing entry of the lane's blocks job .. job + JU - 1 (those
+// below job_end) from their permuted sources.  The sources of a block's
+// entries lie in the same block, and blocks are disjoint.
 template <int JU, int K, int C, typename Mem>
-HT_HD void native_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const NativeGroup& ng,
-                             const NativeOp<K>& op, uint32_t lane, uint32_t job_begin = 0,
-                             uint32_t job_end = 0xffffffffu) {
+HT_HD void native_load_step(const Mem& mem, const ConjGeom<K, C>& g, const NativeGroup& ng, const NativeOp<K>& op,
+                            uint32_t lane, uint32_t job, uint32_t job_end, NativeStep<JU, K>& st) {
   constexpr int D = 1 << K;
   constexpr int KI = K - C;
   const uint32_t nblk = 1u << (2 * g.F);
-  if (job_end > g.jobs) job_end = g.jobs;
-  for (uint32_t job = job_begin; job < job_end; job += JU) {
-    uint32_t bp[JU], bq[JU];
-    bool on[JU];
-    cd x[JU][D * D];
 #pragma unroll
-    for (int j = 0; j < JU; ++j) {
-      const uint32_t b = (job + j) * 64u + lane;
-      uint32_t pidx, qidx;
-      lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
-      bp[j] = deposit_free<KI>(pidx, g.ipos);
-      bq[j] = deposit_free<KI>(qidx, g.ipos);
-      on[j] = job + j < job_end && b < nblk && !(ng.diag && bp[j] < bq[j]);
-      if (on[j]) {
-#pragma unroll
-        for (int u = 0; u < D; ++u)
-#pragma unroll
-          for (int v = 0; v < D; ++v)
-            if (op.act(u, v))
-              x[j][u * D + v] = native_load<K, C>(mem, g, ng, bp[j], bq[j], op.perm[u], op.perm[v]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < JU; ++j) {
-      if (!on[j]) continue;
+  for (int j = 0; j < JU; ++j) {
+    const uint32_t b = (job + j) * 64u + lane;
+    uint32_t pidx, qidx;
+    lane_block(b, g.F, g.s, g.ilv, pidx, qidx);
+    st.bp[j] = deposit_free<KI>(pidx, g.ipos);
+    st.bq[j] = deposit_free<KI>(qidx, g.ipos);
+    st.on[j] = job + j < job_end && b < nblk && !(ng.diag && st.bp[j] < st.bq[j]);
+    if (st.on[j]) {
 #pragma unroll
       for (int u = 0; u < D; ++u)
 #pragma unroll
         for (int v = 0; v < D; ++v)
-          if (op.act(u, v)) {
-            const cd c = op.coef(u, v);
-            // a coefficient of exactly one moves the entry unchanged (bitwise)
-            const bool one = c.re == 1.0 && c.im == 0.0;
-            native_store<K, C>(mem, g, ng, bp[j], bq[j], u, v,
-                               one ? x[j][u * D + v] : cmul(c, x[j][u * D + v]));
-          }
+          if (op.act(u, v))
+            st.x[j][u * D + v] = native_load<K, C>(mem, g, ng, st.bp[j], st.bq[j], op.perm[u], op.perm[v]);
     }
+  }
+}
+
+// The products with the coefficients, written to the entries themselves.
+template <int JU, int K, int C, typename Mem>
+HT_HD void native_store_step(const Mem& mem, const ConjGeom<K, C>& g, const NativeGroup& ng, const NativeOp<K>& op,
+                             const NativeStep<JU, K>& st) {
+  constexpr int D = 1 << K;
+#pragma unroll
+  for (int j = 0; j < JU; ++j) {
+    if (!st.on[j]) continue;
+#pragma unroll
+    for (int u = 0; u < D; ++u)
+#pragma unroll
+      for (int v = 0; v < D; ++v)
+        if (op.act(u, v)) {
+          const cd c = op.coef(u, v);
+          // a coefficient of exactly one moves the entry unchanged (bitwise)
+          const bool one = c.re == 1.0 && c.im == 0.0;
+          native_store<K, C>(mem, g, ng, st.bp[j], st.bq[j], u, v,
+                             one ? st.x[j][u * D + v] : cmul(c, st.x[j][u * D + v]));
+        }
+  }
+}
+
+// All blocks one lane owns in the current group, JU at a time: every
+// changing entry of JU blocks loaded first, then written.
+template <int JU, int K, int C, typename Mem>
+HT_HD void native_group_lane(const Mem& mem, const ConjGeom<K, C>& g, const NativeGroup& ng,
+                             const NativeOp<K>& op, uint32_t lane, uint32_t job_begin = 0,
+                             uint32_t job_end = 0xffffffffu) {
+  if (job_end > g.jobs) job_end = g.jobs;
+  for (uint32_t job = job_begin; job < job_end; job += JU) {
+    NativeStep<JU, K> st;
+    native_load_step<JU, K, C>(mem, g, ng, op, lane, job, job_end, st);
+    native_store_step<JU, K, C>(mem, g, ng, op, st);
   }
 }
 

@@ -48,6 +48,37 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The native pass in workgroup-wide steps (k <= 2): the 16 waves of a
+// workgroup take (group, step) items in the order of sync_item, load every
+// changing entry of their blocks, meet at a barrier, then write them, as
+// conj_sync_kernel does for the conjugation pass.  Same per-lane body:
+// bitwise the same results.
+template <typename T, int K, int C, int MODE>
+__global__ void __launch_bounds__(1024)
+    native_sync_kernel(typename store2<T>::type* __restrict__ h, ConjGeom<K, C> g, NativeOp<K> op, int r, int ps) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr uint32_t wpb = 16;
+  const DirectMem<T, MODE> mem{h};
+  constexpr int JU = native_unroll(K);
+  const uint32_t steps = (g.jobs + JU - 1) / JU;  // a power of two
+  const int sl = 31 - __builtin_clz(steps);
+  const uint64_t nu = sync_units(g.ngroups, sl, wpb, r, ps);
+  // the loop bound is the same for every wave of the workgroup (barrier)
+  for (uint64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    uint64_t grp;
+    uint32_t step;
+    sync_item(u, wib, wpb, sl, r, ps, grp, step);
+    const bool valid = grp < g.ngroups;
+    const NativeGroup ng = native_group<C>(valid ? grp : 0);
+    NativeStep<JU, K> st;
+    const uint32_t j0 = step * JU;
+    native_load_step<JU, K, C>(mem, g, ng, op, lane, j0, valid ? j0 + JU : j0, st);
+    __syncthreads();
+    native_store_step<JU, K, C>(mem, g, ng, op, st);
+  }
+}
+
 template <typename T, int K, int C>
 static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const double* coef_dev,
                            int num_cu, hipStream_t s) {
@@ -78,6 +109,49 @@ static hipError_t launch_t(void* buf, int n, int m, const PreparedOp& pop, const
     // whole 128-byte lines
     constexpr int KI = K - C;
     mode = (sizeof(T) == 8 && (KI == 0 || g.ipos[0] >= 3)) ? 3 : 0;
+  }
+  // Workgroup-wide steps for complex128 operators of 1 GiB and more whose
+  // highest tile-selecting target is at tile bit 4 or above and with no
+  // intra target below bit 3, in the item order of the conjugation pass
+  // (ht_conj.hip): quarters of every other group for one tile-selecting
+  // target, whole groups for two.  Measured with CNOT at n = 16: targets
+  // (8, 9) .. (14, 15) 11.4 -> 10.6-10.9 ms; nearer the tile bits, (4, 5) ..
+  // (7, 8), the grid-stride kernel stayed faster (10.3-11.5 ms against
+  // 11.5-12.6).
+  if constexpr (K <= 2 && C > 0) {
+    constexpr int KI = K - C;
+    const int low = KI > 0 ? g.ipos[0] : 99;
+    const uint64_t nent = ((1ull << n) * ((1ull << n) + (1ull << g.m))) >> 1;
+    const bool big = sizeof(T) == 8 && nent * 2 * sizeof(T) >= (1ull << 30);
+    const int far = g.cpos[C - 1] >= 4 ? 1 : 0;
+    int sw = tuning().sync_waves;
+    if (sw < 0) sw = (big && low >= 3 && far) ? 16 : 0;
+    if (sw > 0 && (mode == 0 || mode == 3)) {
+      int ord = tuning().sync_order;
+      if (ord < 0) ord = C == 1 ? (far ? 2 : 1) : (far ? 0 : 1);
+      if (ord > 2) ord = 2;
+      ConjGeom<K, C> gs = g;
+      int ilv = tuning().sync_interleave;
+      if (ilv < 0) ilv = (ord != 0 || C == 2) ? 0 : (use_interleave((int)sizeof(T) * 2) ? 1 : 0);
+      gs.ilv = ilv != 0;
+      const uint32_t nsteps = (uint32_t)((g.jobs + JU - 1) / JU);
+      const int sl = 31 - __builtin_clz(nsteps);
+      const int rmax = sl < 4 ? sl : 4;
+      int r = g.F - g.s - (JU == 4 ? 2 : JU == 2 ? 1 : 0);
+      if (ord == 0 || r > rmax) r = rmax;
+      if (r < 0) r = 0;
+      const int ps = ord == 2 ? 1 : 0;
+      uint64_t wg = sync_units(g.ngroups, sl, 16u, r, ps);
+      const uint64_t wcap = tuning().sync_grid > 0 ? (uint64_t)tuning().sync_grid
+                            : ord != 0             ? (uint64_t)num_cu * 3u / 4u
+                                                   : (uint64_t)num_cu;
+      if (wg > wcap) wg = wcap;
+      if (mode == 3)
+        hipLaunchKernelGGL((native_sync_kernel<T, K, C, 3>), dim3((unsigned)wg), dim3(1024), 0, s, hp, gs, op, r, ps);
+      else
+        hipLaunchKernelGGL((native_sync_kernel<T, K, C, 0>), dim3((unsigned)wg), dim3(1024), 0, s, hp, gs, op, r, ps);
+      return hipGetLastError();
+    }
   }
   const dim3 grid((unsigned)wgs), block(threads);
   if constexpr (K == 3) {

@@ -98,6 +98,46 @@ def test_native_agrees_with_generic_pass(ht):
         ht.set_tuning("native", 2)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_native_step_kernel_bitwise_equal(ht, dtype):
+    """The native pass in workgroup-wide steps (native_sync_kernel, k <= 2,
+    a tile-selecting target) gives bitwise the grid-stride native pass's
+    storage for every gate of the set on intra, tile-selecting and mixed
+    target pairs, in the three item orders and with 16 waves per workgroup,
+    at tile edges 8 and 32 (n = 9: tile bits up to 5)."""
+    rng = synth.make_rng(1410)
+    n = 9
+    H = synth.random_hermitian_dense(n, rng)
+    cases = []
+    for t in ([3], [5], [8], [2, 7], [6, 8], [8, 5], [4, 6]):
+        for g in gate_set(len(t), rng):
+            cases.append((t, g, int(rng.integers(2))))
+    tunings = [{"sync_waves": 16, "sync_order": o} for o in (0, 1, 2)] + [{"sync_waves": 16, "sync_grid": 7}]
+    try:
+        for m in (3, 5):
+            base = []
+            ht.set_tuning("sync_waves", 0)
+            for t, g, pic in cases:
+                h = ht.Herm(n, m, dtype).init_dense(H)
+                h.apply_channel(t, g, pic)
+                base.append(h.raw_entries())
+                h.close()
+            for tune in tunings:
+                for key, v in tune.items():
+                    ht.set_tuning(key, v)
+                for (t, g, pic), want in zip(cases, base):
+                    h = ht.Herm(n, m, dtype).init_dense(H)
+                    h.apply_channel(t, g, pic)
+                    assert np.array_equal(h.raw_entries(), want), (dtype, m, t, tune)
+                    h.close()
+                for key in tune:
+                    ht.set_tuning(key, -1 if key != "sync_grid" else 0)
+            ht.set_tuning("sync_waves", -1)
+    finally:
+        for key, v in (("sync_waves", -1), ("sync_order", -1), ("sync_grid", 0)):
+            ht.set_tuning(key, v)
+
+
 def test_native_c64_one_rounding(ht):
     rng = synth.make_rng(1500)
     n, m = 7, 3
