@@ -238,7 +238,9 @@ def test_k3_bad_kraus_count_leaves_state(ht):
 @pytest.mark.parametrize("n", [14, 16])
 def test_native_full_size_sampled_blocks(ht, n):
     """Full-size operators at the benchmark's tile edge: native ops at intra
-    and tile-selecting positions on 1500 sampled blocks each, plus trace."""
+    and tile-selecting positions on 1500 sampled blocks each (k <= 2 with a
+    tile-selecting target at tile bit 4 or above in workgroup steps, nearer
+    ones grid-stride), plus trace."""
     rng = synth.make_rng(1800 + n)
     h = ht.Herm(n, 5).init_lowrank(synth.ginibre_factor(n, 16, rng))
     h.scale(1.0 / h.trace())
@@ -248,6 +250,8 @@ def test_native_full_size_sampled_blocks(ht, n):
         synth.random_ops.channel_op([7], synth.dephasing_kraus(0.2)),
         synth.random_ops.unitary_op([4, n - 3], synth.cnot_matrix()),
         synth.random_ops.unitary_op([9, 6], synth.permutation_gate("SWAP")),
+        synth.random_ops.unitary_op([n - 1, n - 2], synth.cnot_matrix()),      # workgroup steps, top tiles
+        synth.random_ops.unitary_op([5, 6], synth.permutation_gate("CZ")),     # grid-stride (near)
         synth.random_ops.unitary_op([1, 2, 4], synth.permutation_gate("TOFFOLI")),
         synth.random_ops.unitary_op([0, 8, n - 1], synth.permutation_gate("FREDKIN")),
         synth.random_ops.unitary_op([n - 1, 10, 5], synth.permutation_gate("TOFFOLI")),
