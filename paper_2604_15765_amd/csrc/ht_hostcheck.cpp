@@ -299,6 +299,12 @@ int htc_emulate_conj(double* raw, uint64_t nelems, int n, int tile_log2, int k, 
   return 0;
 }
 
+// lane_block for block index b: the block's base row and column indices
+// (pidx, qidx) in [0, 2^F).
+void htc_lane_block(uint32_t b, int F, int s, int ilv, uint32_t* pidx, uint32_t* qidx) {
+  ht::lane_block(b, F, s, ilv != 0, *pidx, *qidx);
+}
+
 // The item order of the workgroup-wide step kernel: for every unit
 // u < sync_units(...) and wave w < wpb, grp[u * wpb + w] and step[...] as
 // sync_item gives them.  Returns the number of units, or 0 when they exceed

@@ -424,3 +424,38 @@ def test_step_kernel_item_orders_cover_every_item_once():
                             it = np.arange(nu * wpb, dtype=np.uint64)
                             assert np.array_equal(g, it >> np.uint64(sl))
                             assert np.array_equal(s, (it & np.uint64((1 << sl) - 1)).astype(np.uint32))
+
+
+def test_quarter_order_steps_cover_one_row_band():
+    """The step kernel's quarter order gives a workgroup step the 2^r
+    consecutive steps of a group with r = F - s - log2(blocks per lane and
+    step) (complex128 JU = 4 for k = 1, 1 for k = 2; row-run patches,
+    s = 3).  Those steps must cover exactly one 8-row band of base row
+    indices (the same high bits for every block) and every base column.
+    With no intra target (F = 5 at M = 32) that is one 4 KiB run of each
+    stored tile, so all runs of a workgroup step share address bits
+    12-13."""
+    if not os.path.exists(SO):
+        pytest.skip("_hostcheck.so not built")
+    f = ctypes.CDLL(SO).htc_lane_block
+    f.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                  ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
+    p, q = ctypes.c_uint32(), ctypes.c_uint32()
+    # (F, JU): k = 1 one tile-selecting target (F = m = 5), k = 2 two (F = 5),
+    # k = 2 one intra + one tile-selecting (F = 4)
+    for F, ju in ((5, 4), (5, 1), (4, 1)):
+        s = min(3, F)
+        jobs = (1 << (2 * F)) // 64
+        steps = jobs // ju
+        r = F - s - {4: 2, 2: 1, 1: 0}[ju]
+        per = 1 << r  # steps per unit
+        for u in range(steps // per):
+            rows, cols = set(), set()
+            for step in range(u * per, (u + 1) * per):
+                for job in range(step * ju, step * ju + ju):
+                    for lane in range(64):
+                        f(job * 64 + lane, F, s, 0, ctypes.byref(p), ctypes.byref(q))
+                        rows.add(p.value)
+                        cols.add(q.value)
+            assert cols == set(range(1 << F)), (F, ju, u)
+            assert len(rows) == 8 and len({r_ >> 3 for r_ in rows}) == 1, (F, ju, u, sorted(rows))
