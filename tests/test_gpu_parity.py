@@ -603,6 +603,7 @@ def test_full_size_sampled_blocks(ht, n, dtype):
         synth.random_ops.unitary_op([4, 5], synth.haar_unitary(4, rng)),             # k=2 c=1
         synth.random_ops.unitary_op([n - 1, 6], synth.haar_unitary(4, rng)),         # k=2 c=2
         synth.random_ops.channel_op([7, 12], synth.random_kraus_set(2, 3, rng)),     # k=2 c=2 transfer
+        synth.random_ops.channel_op([1, 3], synth.random_kraus_set(2, 3, rng)),      # k=2 c=0 transfer (staged)
         synth.random_ops.unitary_op([0, n - 2], synth.cnot_matrix()),                # k=2 c=1
     ]
     if dtype == "c64":
